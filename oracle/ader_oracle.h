@@ -1,0 +1,90 @@
+/*
+ * FP64 CPU oracle for the ADER-DG hot path (test infrastructure).
+ *
+ * This is NOT part of the product.  Only the tests, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it.  It shares no code with the
+ * HIP library: it has its own Gauss-Legendre rule, Lagrange basis, operator
+ * tables, PDE fluxes and Riemann solver.
+ *
+ * What it computes (Dumbser, Fambri, Tavelli, Bader, Weinzierl, "Efficient
+ * implementation of ADER discontinuous Galerkin schemes for a scalable
+ * hyperbolic PDE engine", 2018):
+ *   - PDE class  Q_t + div F(Q) + B(Q).grad Q = S(Q)            (Sec. 2, eq. pde)
+ *   - nodal tensor basis on N+1 Gauss-Legendre nodes on [0,1]   (Sec. 2.1, eq. ansatz.uh)
+ *   - element-local space-time predictor, Picard iteration       (Sec. 2.2, eqs. spacetime, pde.st2)
+ *   - corrector with path-conservative Rusanov jump term         (Sec. 2.1, eqs. pde.nc.gw2, pc.scheme, rusanov)
+ *   - CFL time step, alpha = cfl*alpha_N below 1/(2N+1)          (Sec. 3, CFL condition)
+ *
+ * Layout (shared with the library's public layout, which is part of the
+ * interface, not of the arithmetic):
+ *   u[e][v][k]      e = ix + nx*(iy + ny*iz),  k = k1 + n*(k2 + n*k3), n = N+1
+ *   qhat[e][v][l0][k]   space-time predictor DOFs, l0 = time node
+ *
+ * Parity status: every function below is pinned by a CPU test (see the
+ * oracle tests) except the absolute error values of the isentropic vortex,
+ * which the paper quotes from another work without its parameters
+ * (parity unpinned for those absolute values; only the orders are pinned).
+ */
+#ifndef ADER_ORACLE_H
+#define ADER_ORACLE_H
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_MAXN 8 /* largest n = N+1 */
+
+enum { ORC_EULER = 0, ORC_ELASTIC = 1 };
+
+typedef struct {
+  int dim;          /* 2 or 3 (elasticity: 3) */
+  int N;            /* polynomial degree, 0..7 */
+  int nel[3];       /* elements per axis (nel[2] = 1 when dim = 2) */
+  double lo[3], hi[3];
+  int pde;          /* ORC_EULER or ORC_ELASTIC */
+  double gamma;     /* Euler: ratio of specific heats */
+  const double *material; /* ELASTIC: [E][3] = (rho, lambda, mu) */
+  int picard;       /* number of Picard sweeps; 0 -> N+1 */
+  double cfl;       /* dt = cfl*alpha_N / max_e sum_d lambda_d/h_d */
+  int guess;        /* initial guess of the Picard iteration: 0 = u_h(t^n) */
+} orc_problem;
+
+/* 1-D basis on [0,1] (Sec. 2.1). */
+int orc_gauss_legendre(int n, double *xi, double *w);
+double orc_lagrange(int n, const double *xi, int k, double x);
+double orc_lagrange_deriv(int n, const double *xi, int k, double x);
+/* Operator tables, all n x n row-major except F0/F1 (length n):
+ *   Dhat[k][j] = phi_j'(xi_k); F0[k] = phi_k(0); F1[k] = phi_k(1);
+ *   K[j][k] = int phi_j phi_k' = w_j phi_k'(xi_j);  K1 = F1 F1^T - K^T;
+ *   T = K1^{-1} W  (time operator of the predictor). */
+int orc_operators(int N, double *xi, double *w, double *Dhat, double *F0,
+                  double *F1, double *K, double *K1, double *T);
+
+/* Number of variables m of the problem. */
+int orc_nvar(const orc_problem *p);
+/* Stability coefficient alpha_N of the CFL rule (1-D von Neumann limit of
+ * the scheme, rounded down; always below the paper's bound 1/(2N+1) for N>=2). */
+double orc_stability_alpha(int N);
+/* Unclipped CFL step (Sec. 3): dt = cfl*alpha_N / max_e sum_d lambda_d/h_d.  Returns a negative value when a node is
+ * non-finite or non-physical (rho <= 0 or p <= 0). */
+double orc_cfl_dt(const orc_problem *p, const double *u);
+/* Space-time predictor (Sec. 2.2) for every element; qhat is [E][m][n][n^d].
+ * Returns 0 on success. */
+int orc_predictor(const orc_problem *p, const double *u, double dt, double *qhat);
+/* Picard sweeps actually needed until max|dq| <= tol*max|q| (diagnostic). */
+int orc_predictor_converge(const orc_problem *p, const double *u, double dt,
+                           double tol, int max_sweeps, double *qhat);
+/* Corrector (Sec. 2.1, eq. pde.nc.gw2): unew = u + dt*R(qhat). */
+int orc_corrector(const orc_problem *p, const double *u, const double *qhat,
+                  double dt, double *unew);
+/* One full step with dt = min(cfl dt, t_end - t); updates u and *t in place.
+ * Returns 0, or -1 on a non-physical state. *dt_out may be NULL. */
+int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *dt_out);
+/* Integral of every variable over the domain (Neumaier summation): sums[m]. */
+int orc_totals(const orc_problem *p, const double *u, double *sums);
+/* Threads the OpenMP runtime will use. */
+int orc_num_threads(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
