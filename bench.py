@@ -1,0 +1,209 @@
+"""Benchmark of the ADER-DG step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16]
+
+Workload: 3-D compressible Euler (gamma = 1.4) on the periodic unit cube,
+64^3 elements, degree N = 4 (125 nodes per element, 32.8 M spatial DOFs),
+density wave rho = 1 + 0.2 sin(2 pi (x+y+z)) with u = (1,1,1), p = 1 plus
+seeded 1e-3 uniform noise on rho, CFL 0.9.  A step is one full ADER-DG step
+(time-step reduction, predictor, face integrals, update) on inputs resident
+in HBM.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DOF-updates/sec/GPU for ADER-DG step, FP32-MFMA vs FP64, at stated L2 error"
+PEAK = {"fp64_valu": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2500.0, "hbm": 8000.0}
+
+
+def predictor_flops(d: int, N: int, m: int, sweeps: int, cF: int = 31) -> float:
+    """Algorithmic (sum-factorised) flops of the predictor for one element of
+    3-D Euler, counting a multiply-add as 2 flops and a division as 1:
+      per sweep: cF flux flops per space-time node (the primitive variables
+        once, 7 flops per axis), d axis contractions and 1 time contraction
+        at 2n flops per output, and 2 flops per output for u + dt * (...);
+      outputs: one more flux evaluation, the time average (2 flops per
+        output and axis), the volume contraction (2n per output and axis),
+        u* = u + dt V and the 2d face traces (2n per trace value)."""
+    n = N + 1
+    nst = n ** (d + 1)
+    nd = n ** d
+    sweep = cF * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
+    outputs = cF * nst + 2 * m * d * nst + d * 2 * n * m * nd + 2 * m * nd + 2 * d * 2 * n * m * nd
+    return sweeps * sweep + outputs
+
+
+def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
+    """Algorithmic HBM bytes per element per step, per stage."""
+    n = N + 1
+    nd = n ** d
+    nf = nd // n
+    u = 8 * m * nd
+    trace = trace_bytes * m * nd            # one face trace block of one element
+    g = 8 * m * nf                           # one face integral block
+    return {
+        "cfl": u,
+        "predictor": u + u + 2 * d * trace,  # read u, write u*, write 2d traces
+        "face": d * (2 * trace + g),          # read both traces, write G, per axis
+        "update": u + 2 * d * g + u,          # read u* and the 2d face blocks, write u
+    }
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1808_03788_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(prec: str):
+    """HBM bytes per predictor launch from the committed PMC summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_predictor_euler3d_N4_64.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("source_hash") != source_hash():
+        return None
+    return rec.get(prec, {}).get("bytes_per_launch")
+
+
+def cpu_baseline(seconds: float = 12.0) -> dict:
+    """The FP64 oracle on a bounded sample of the same workload: a periodic
+    16^3-element box with the same degree, PDE and initial-data recipe, as
+    many steps as fit in about `seconds` (at least one)."""
+    import oracle
+    from paper_1808_03788_amd import inputs as I
+    prob = I.density_wave_problem(nel=16, N=4)
+    u = I.density_wave(prob)
+    t, steps = 0.0, 0
+    t0 = time.perf_counter()
+    while True:
+        u, t, _ = oracle.step(prob, u, t, 1e9)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or steps >= 50:
+            break
+    return {
+        "value": prob.E * prob.nd * steps / el,
+        "unit": "DOF-updates/s",
+        "cores": oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"3-D Euler density wave, 16^3 elements, N=4, {steps} steps, "
+                  f"{el:.1f} s, plain C -O2 FP64 with OpenMP over elements",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--nel", type=int, default=64)
+    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; "
+                                   "multi-GPU sharding is not built (--gpus 1)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1808_03788_amd import ader
+    from paper_1808_03788_amd import inputs as I
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prob = I.density_wave_problem(nel=args.nel, N=args.degree, prec=args.prec)
+    u0 = I.density_wave(prob)
+    ctx = ader.Context([prob])
+    u = ctx.upload([u0])
+    del u0
+    for _ in range(args.warmup):
+        ctx.step(u, 1e9)
+    torch.cuda.synchronize()
+    ctx.cfl_dt(u)                        # surfaces a latched non-finite state
+    ader.ader_profile(ctx.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.step(u, 1e9)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stages = ader.ader_stage_times(ctx.ctx)
+    ader.ader_profile(ctx.ctx, False)
+    t_sim = ctx.time()[0]
+    finite = bool(torch.isfinite(u).all().item())
+
+    dofs = prob.E * prob.nd
+    value = dofs * args.steps / elapsed
+    sweeps = prob.picard or prob.N + 1
+    flops = predictor_flops(3, prob.N, prob.m, sweeps) * prob.E
+    pred_ms = stages["predictor"][0] / max(1, stages["predictor"][1])
+    achieved = flops / (pred_ms * 1e-3) / 1e12
+    peak_key = "fp64_valu" if args.prec == "fp64" else f"{args.prec}_mfma"
+    bound = "alu" if args.prec == "fp64" else "mfma"
+    traffic = traffic_from_profiles(args.prec)
+    per_el = step_bytes(3, prob.N, prob.m, 8 if args.prec == "fp64" else 4)
+    stage_report = {}
+    for k, (ms, cnt) in stages.items():
+        avg = ms / max(1, cnt)
+        gbs = per_el[k] * prob.E / (avg * 1e-3) / 1e9 if avg > 0 else None
+        stage_report[k] = {"avg_ms": round(avg, 4), "alg_GB_per_s": round(gbs, 1) if gbs else None}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else f"{args.prec}+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D Euler density wave, periodic unit cube, {args.nel}^3 elements, "
+                        f"N={prob.N}, CFL 0.9, 1e-3 seeded noise",
+            "elements": prob.E, "degree": prob.N, "dofs": dofs, "variables": prob.m,
+            "picard_sweeps": sweeps, "predictor_precision": args.prec,
+        },
+        "roofline": {
+            "bound": bound,
+            "kernel": "k_predictor",
+            "achieved": round(achieved, 2),
+            "peak": PEAK[peak_key],
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK[peak_key], 4),
+            "traffic": traffic,
+            "alg_flops_per_launch": flops,
+            "avg_launch_ms": round(pred_ms, 4),
+        },
+        "stages": stage_report,
+        "state_finite": finite,
+        "sim_time": t_sim,
+    }
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,172 @@
+/*
+ * ader.h -- C ABI of the ADER-DG hot path on MI355X (gfx950).
+ *
+ * The library advances hyperbolic systems
+ *     Q_t + div F(Q) + B(Q).grad Q = S(Q)                      (Sec. 2, eq. pde)
+ * on periodic Cartesian meshes with the unlimited ADER-DG scheme of Dumbser,
+ * Fambri, Tavelli, Bader and Weinzierl (2018): a nodal tensor basis on the
+ * N+1 Gauss-Legendre points of [0,1] (Sec. 2.1, eq. ansatz.uh), the
+ * element-local space-time predictor solved by Picard iteration (Sec. 2.2,
+ * eqs. spacetime and pde.st2) and the one-step corrector with the
+ * path-conservative Rusanov jump term (Sec. 2.1, eqs. pde.nc.gw2, pc.scheme,
+ * rusanov).  Two systems are built in: the compressible Euler equations
+ * (Sec. 3.1, eq. euler) and linear elasticity in velocity-stress form
+ * (Sec. 3.2, eqs. 3.00-3.1 with volume fraction 1).
+ *
+ * Conventions
+ *   - Every call returns ader_status; nothing throws across the ABI.
+ *   - All state pointers (u, dt_dev, qhat_out) are DEVICE pointers on the
+ *     device that was current at ader_create; host pointers are named *_host.
+ *   - A context is bound to one HIP stream and is not thread-safe.  Calls
+ *     enqueue work on that stream and return without synchronising, except
+ *     where a host output is requested (they then synchronise the stream).
+ *   - Errors are reported synchronously for argument checks
+ *     (ADER_ERR_INVALID / ADER_ERR_UNSUPPORTED).  Non-finite or non-physical
+ *     states (NaN/Inf, density <= 0, pressure <= 0) are detected on the
+ *     device by the time-step reduction; asynchronous calls latch the flag and
+ *     the next synchronising call returns ADER_ERR_NONFINITE (and clears it).
+ *     When the flag is raised the step size of that problem is set to 0.
+ *   - ader_last_error(ctx) returns a message for the last failing call.
+ *
+ * State layout (caller-owned, FP64, one contiguous device buffer holding all
+ * problems, each at the offset returned by ader_layout):
+ *     u[e][v][k],  e = ix + nx*(iy + ny*iz),  k = k1 + n*(k2 + n*k3),  n = N+1
+ *   node k of element e sits at x_a = lo_a + (i_a + xi_{k_a}) * h_a with xi
+ *   the Gauss-Legendre points of [0,1] and h_a = (hi_a - lo_a)/nelem_a.
+ *   Variables: Euler (rho, rho*v_1..rho*v_d, rho*E); elasticity
+ *   (v_x, v_y, v_z, s_xx, s_yy, s_zz, s_xy, s_yz, s_xz).
+ */
+#ifndef ADER_H
+#define ADER_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ader_ctx ader_ctx; /* opaque; owns every scratch buffer */
+
+typedef enum {
+  ADER_OK = 0,
+  ADER_ERR_INVALID = 1,     /* bad argument: NULL pointer, size, dimension, ... */
+  ADER_ERR_UNSUPPORTED = 2, /* valid but not built: degree > 7, LDS too small, ... */
+  ADER_ERR_OOM = 3,         /* device allocation failed */
+  ADER_ERR_DEVICE = 4,      /* a HIP call failed */
+  ADER_ERR_NONFINITE = 5    /* NaN/Inf or non-physical state met on the device */
+} ader_status;
+
+typedef enum { ADER_EULER = 0, ADER_ELASTIC = 1 } ader_pde;
+
+/* Arithmetic of the predictor's Picard sweeps.  ADER_FP64: every sweep in
+ * FP64.  ADER_FP32: sweeps 1..P-1 in FP32 (operator contractions on MFMA
+ * with FP32 accumulation), the last sweep in FP64.  ADER_BF16: like FP32 but
+ * the contraction inputs are rounded to bfloat16.  The corrector's update
+ * u^{n+1} = u^n + dt*R, the time-step reduction and the conservation sums are
+ * FP64 in every mode. */
+typedef enum { ADER_FP64 = 0, ADER_FP32 = 1, ADER_BF16 = 2 } ader_prec;
+
+typedef struct {
+  int32_t dim;          /* 2 or 3 (elasticity: 3) */
+  int32_t degree;       /* N in [0,7]; supported N depends on dim/pde/prec (LDS) */
+  int32_t nelem[3];     /* elements per axis, >= 1 (nelem[2] ignored for dim = 2) */
+  double lo[3], hi[3];  /* box; periodic in every axis */
+  int32_t pde;          /* ader_pde */
+  double gamma;         /* Euler: ratio of specific heats (> 1) */
+  const double *material; /* ELASTIC: HOST array [E][3] = (rho, lambda, mu),
+                             copied at create; ignored for Euler */
+  int32_t prec;         /* ader_prec */
+  int32_t picard_iters; /* Picard sweeps P; 0 -> N+1 */
+  double cfl;           /* dt = cfl * alpha_N / max_e sum_d lambda_d / h_d,  0 < cfl <= 1 */
+} ader_problem;
+
+/* Create a context for `nprob` independent problems (Sec. 2; the problems
+ * share nothing but the stream).  `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  Device memory for traces, face integrals and the
+ * predictor's output is allocated here and owned by the context.  The
+ * simulation time of every problem starts at 0. */
+ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stream,
+                        ader_ctx **out);
+/* Free everything the context owns.  NULL is accepted. */
+ader_status ader_destroy(ader_ctx *ctx);
+
+/* Offset and length (in doubles) of problem `prob` inside the state buffer;
+ * the buffer must hold at least offset+count doubles for every problem. */
+ader_status ader_layout(const ader_ctx *ctx, int32_t prob, int64_t *offset, int64_t *count);
+/* Total number of doubles of the state buffer. */
+ader_status ader_state_size(const ader_ctx *ctx, int64_t *count);
+
+/* Time step of every problem from the state u (Sec. 3, CFL condition):
+ *   dt_p = cfl * alpha_N / max_e sum_a (max_{k in e} |lambda_a(u_k)|) / h_a,
+ * with |lambda_a| = |v_a| + c for Euler and the P-wave speed for elasticity;
+ * alpha_N is the 1-D von Neumann stability limit of the scheme (below the
+ * paper's bound 1/(2N+1)).  The result stays on the device and is the step
+ * used by a following ader_predictor/ader_corrector with dt_dev = NULL.  If
+ * dt_host (host, [nprob]) is not NULL the call synchronises and copies it. */
+ader_status ader_cfl_dt(ader_ctx *ctx, const double *u, double *dt_host);
+
+/* Space-time predictor of every element (Sec. 2.2, eq. pde.st2): Picard
+ * iteration q <- u + dt*T*R(q) from q = u, R the collocated right-hand side
+ * S - div F - B.grad q.  Also evaluates the predictor's volume integrals and
+ * the boundary-extrapolated traces on all faces into context scratch.
+ *   u        device [state], read only
+ *   dt_dev   device [nprob] step sizes, or NULL for the context's step
+ *   qhat_out device [E][m][N+1][(N+1)^d] per problem at the same offsets
+ *            scaled by (N+1) (debug / test output), or NULL. */
+ader_status ader_predictor(ader_ctx *ctx, const double *u, const double *dt_dev,
+                           double *qhat_out);
+/* Offset (in doubles) of problem `prob` inside a qhat_out buffer, and its size. */
+ader_status ader_qhat_layout(const ader_ctx *ctx, int32_t prob, int64_t *offset, int64_t *count);
+
+/* Corrector (Sec. 2.1, eq. pde.nc.gw2) with the last predictor's output:
+ * face integrals of the path-conservative Rusanov jump term (eqs. pc.scheme,
+ * rusanov) at every face node and time node, then the FP64 update
+ *   u <- u + dt * (V - lifted face terms) / (diagonal mass).
+ * dt_dev must equal the one given to ader_predictor (NULL = context's). */
+ader_status ader_corrector(ader_ctx *ctx, double *u, const double *dt_dev);
+
+/* One full step of every problem: time step (clipped so that the step ends
+ * exactly at t_end_host[p]; a problem already at t_end takes dt = 0),
+ * predictor, corrector, time advance.  Host-synchronisation free, so it can
+ * be captured into a hipGraph (the captured t_end values are then fixed). */
+ader_status ader_step(ader_ctx *ctx, double *u, const double *t_end_host);
+
+/* Current simulation time of every problem (host [nprob]); synchronises and
+ * reports a latched ADER_ERR_NONFINITE. */
+ader_status ader_time(ader_ctx *ctx, double *t_host);
+/* Overwrite the simulation times (host [nprob]), e.g. to resume a run. */
+ader_status ader_set_time(ader_ctx *ctx, const double *t_host);
+/* Step sizes of the last ader_cfl_dt/ader_step (host [nprob]); synchronises. */
+ader_status ader_last_dt(ader_ctx *ctx, double *dt_host);
+
+/* Domain integral of every variable, sum_e |Omega_e| sum_k w_k u (FP64,
+ * deterministic order), into host [sum over problems of m]; synchronises. */
+ader_status ader_totals(ader_ctx *ctx, const double *u, double *sums_host);
+
+/* Per-stage device timing of ader_step.  With enable != 0 the context
+ * records HIP events on its own stream at the boundaries of the four stages
+ * of every following ader_step: 0 time-step reduction, 1 predictor, 2 face
+ * integrals, 3 update.  ader_stage_times synchronises and returns, per stage,
+ * the summed elapsed milliseconds (host [4]) and the number of recorded
+ * steps (host [4], may be NULL), then clears the record.  Timing adds one
+ * event record per stage boundary; it is off by default. */
+ader_status ader_profile(ader_ctx *ctx, int32_t enable);
+ader_status ader_stage_times(ader_ctx *ctx, double *ms_host, int64_t *launches_host);
+
+/* Message of the last failing call on this context (never NULL); with
+ * ctx = NULL, the message of the last failed ader_create on this thread. */
+const char *ader_last_error(const ader_ctx *ctx);
+
+/* Host-side queries (no device needed). */
+/* alpha_N of the CFL rule for degree N (see ader_cfl_dt). */
+ader_status ader_stability_alpha(int32_t degree, double *alpha);
+/* The 1-D tables of degree N: Gauss-Legendre points and weights on [0,1]
+ * (n each), derivative matrix Dhat[k][j] = phi_j'(xi_k) and the predictor's
+ * time operator T (n*n each, row-major).  Any output may be NULL. */
+ader_status ader_basis(int32_t degree, double *xi, double *w, double *dhat, double *tmat);
+/* Library version string. */
+const char *ader_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

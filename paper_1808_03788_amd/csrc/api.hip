@@ -1,0 +1,600 @@
+// C ABI of the ADER-DG library: context, argument checks, allocation and
+// the launch sequence of one step.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "ader.h"
+#include "kernel_set.hpp"
+
+using namespace ader;
+
+namespace {
+
+constexpr size_t kLdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kTotBlocks = 512;           // blocks of the conservation-sum reduction
+
+struct ProbState {
+  ader_problem desc{};
+  int D = 0, N = 0, n = 0, m = 0, nd = 0, nst = 0, nf = 0;
+  int64_t E = 0;
+  Geom g{};
+  double h[3] = {1, 1, 1};
+  Ops ops{};
+  double coef = 0.0;  // cfl * alpha_N
+  int sweeps = 0;
+  int64_t u_off = 0, u_cnt = 0, q_off = 0, q_cnt = 0;
+  KernelSet ks{};
+  bool acc_lds = true;
+  size_t shmem = 0;
+  double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
+  double *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  double *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};
+};
+
+}  // namespace
+
+struct ader_ctx {
+  hipStream_t stream = nullptr;
+  int device = 0;
+  std::vector<ProbState> P;
+  double *dt = nullptr, *t = nullptr, *tnext = nullptr;  // device [nprob]
+  unsigned long long *smax = nullptr;                      // device [nprob]
+  int *err = nullptr;                                      // device [1]
+  double *partial = nullptr, *sums = nullptr;              // totals scratch
+  int64_t total_u = 0, total_q = 0, total_m = 0;
+  std::string msg;
+  std::vector<void *> allocs;
+  bool profile = false;
+  std::vector<hipEvent_t> ev_pool, ev_used;  // 5 boundaries per profiled step
+};
+
+namespace {
+
+thread_local std::string g_create_msg = "";  // message of the last failed ader_create
+
+ader_status fail(ader_ctx *c, ader_status s, const std::string &m) {
+  if (c) c->msg = m;
+  return s;
+}
+
+#define HIP_OR_FAIL(ctx, call)                                                          \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(ctx, ADER_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+ader_status dalloc(ader_ctx *c, void **p, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(c, ADER_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->allocs.push_back(*p);
+  return ADER_OK;
+}
+
+KernelSet kernels_for(const ader_problem &d) {
+  if (d.pde == ADER_EULER) return d.dim == 2 ? kernels_euler2(d.degree) : kernels_euler3(d.degree);
+  return kernels_elastic3(d.degree);
+}
+
+ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
+  const std::string w = "problem " + std::to_string(i) + ": ";
+  if (d.dim != 2 && d.dim != 3) return fail(c, ADER_ERR_INVALID, w + "dim must be 2 or 3");
+  if (d.degree < 0) return fail(c, ADER_ERR_INVALID, w + "degree must be >= 0");
+  if (d.degree > 7) return fail(c, ADER_ERR_UNSUPPORTED, w + "degree > 7 is not built");
+  for (int a = 0; a < d.dim; a++) {
+    if (d.nelem[a] < 1) return fail(c, ADER_ERR_INVALID, w + "nelem must be >= 1");
+    if (!(d.hi[a] > d.lo[a]) || !isfinite(d.hi[a] - d.lo[a]))
+      return fail(c, ADER_ERR_INVALID, w + "hi must exceed lo");
+  }
+  if (d.pde != ADER_EULER && d.pde != ADER_ELASTIC) return fail(c, ADER_ERR_INVALID, w + "unknown pde");
+  if (d.pde == ADER_EULER && !(d.gamma > 1.0)) return fail(c, ADER_ERR_INVALID, w + "gamma must exceed 1");
+  if (d.pde == ADER_ELASTIC) {
+    if (d.dim != 3) return fail(c, ADER_ERR_UNSUPPORTED, w + "elasticity is 3-D only");
+    if (!d.material) return fail(c, ADER_ERR_INVALID, w + "elasticity needs a material array");
+    const int64_t E = (int64_t)d.nelem[0] * d.nelem[1] * d.nelem[2];
+    for (int64_t e = 0; e < E; e++) {
+      const double *mt = d.material + 3 * e;
+      if (!(mt[0] > 0.0) || !(mt[2] >= 0.0) || !(mt[1] + 2.0 * mt[2] > 0.0) || !isfinite(mt[0]) ||
+          !isfinite(mt[1]) || !isfinite(mt[2]))
+        return fail(c, ADER_ERR_INVALID, w + "invalid material at element " + std::to_string(e));
+    }
+  }
+  if (d.prec != ADER_FP64 && d.prec != ADER_FP32 && d.prec != ADER_BF16)
+    return fail(c, ADER_ERR_INVALID, w + "unknown precision");
+  if (d.prec != ADER_FP64) return fail(c, ADER_ERR_UNSUPPORTED, w + "only FP64 predictor is built");
+  if (d.picard_iters < 0) return fail(c, ADER_ERR_INVALID, w + "picard_iters must be >= 0");
+  if (!(d.cfl > 0.0) || d.cfl > 1.0) return fail(c, ADER_ERR_INVALID, w + "cfl must be in (0, 1]");
+  return ADER_OK;
+}
+
+__global__ void k_finalize(unsigned long long *smax, int *err, double coef, double t_end,
+                           const double *t, double *dt, double *tnext) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double S = __longlong_as_double((long long)*smax);
+  *smax = 0ull;
+  double d;
+  if (!(S > 0.0) || isinf(S)) {
+    atomicOr(err, 1);
+    d = 0.0;
+  } else {
+    d = coef / S;
+  }
+  if (*err) d = 0.0;
+  const double rem = t_end - *t;
+  double tn = *t + d;
+  if (rem <= d) {  // the last step lands exactly on t_end
+    d = rem > 0.0 ? rem : 0.0;
+    tn = rem > 0.0 ? t_end : *t;
+  }
+  *dt = d;
+  *tnext = tn;
+}
+
+__global__ void k_commit(double *t, const double *tnext, int np) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i < np) t[i] = tnext[i];
+}
+
+// Conservation sums: per-block partial sums in a fixed order, then a
+// sequential pass over the blocks; deterministic for a given grid.
+__global__ void __launch_bounds__(kBlock) k_totals_partial(const double *u, int64_t E, int m, int nd,
+                                                          int n, int D, Ops ops, double vol,
+                                                          double *partial) {
+  __shared__ double red[kBlock];
+  for (int v = 0; v < m; v++) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < E * nd;
+         i += (int64_t)gridDim.x * kBlock) {
+      const int64_t e = i / nd;
+      const int k = (int)(i - e * nd);
+      double wk = vol;
+      int kk = k;
+      for (int a = 0; a < D; a++) {
+        wk *= ops.w[kk % n];
+        kk /= n;
+      }
+      s += wk * u[(e * m + v) * nd + k];
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + v] = red[0];
+    __syncthreads();
+  }
+}
+
+__global__ void k_totals_final(const double *partial, int nblk, int m, double *out) {
+  const int v = threadIdx.x;
+  if (v >= m) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; b++) s += partial[(int64_t)b * m + v];
+  out[v] = s;
+}
+
+int64_t blocks_for(int64_t work) { return (work + kBlock - 1) / kBlock; }
+
+ader_status launch(ader_ctx *c, const void *fn, int64_t grid, size_t shmem, void *arg) {
+  if (grid <= 0) return ADER_OK;
+  if (grid > 0x7fffffff) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
+  void *args[] = {arg};
+  HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kBlock), args, shmem, c->stream));
+  return ADER_OK;
+}
+
+ader_status run_cfl(ader_ctx *c, const double *u, const double *t_end_host) {
+  for (size_t p = 0; p < c->P.size(); p++) {
+    ProbState &s = c->P[p];
+    CflArgs a{};
+    a.g = s.g;
+    for (int i = 0; i < 3; i++) a.h[i] = s.h[i];
+    a.u = u + s.u_off;
+    a.mat = s.mat;
+    a.smax_bits = c->smax + p;
+    a.err = c->err;
+    ader_status st = launch(c, s.ks.cfl, (s.E + kBlock / 64 - 1) / (kBlock / 64), 0, &a);
+    if (st) return st;
+    const double te = t_end_host ? t_end_host[p] : INFINITY;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, c->stream, c->smax + p, c->err, s.coef, te,
+                       c->t + p, c->dt + p, c->tnext + p);
+    HIP_OR_FAIL(c, hipGetLastError());
+  }
+  return ADER_OK;
+}
+
+ader_status run_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat) {
+  for (size_t p = 0; p < c->P.size(); p++) {
+    ProbState &s = c->P[p];
+    PredArgs a{};
+    a.ops = s.ops;
+    a.g = s.g;
+    a.u = u + s.u_off;
+    a.dt = (dt_dev ? dt_dev : c->dt) + p;
+    a.mat = s.mat;
+    a.ustar = s.ustar;
+    for (int ax = 0; ax < 3; ax++)
+      for (int sd = 0; sd < 2; sd++) a.trace[ax][sd] = s.trace[ax][sd];
+    a.qhat = qhat ? qhat + s.q_off : nullptr;
+    a.acc_glob = s.acc;
+    a.sweeps = s.sweeps;
+    ader_status st = launch(c, s.acc_lds ? s.ks.pred_lds : s.ks.pred_glob, s.E, s.shmem, &a);
+    if (st) return st;
+  }
+  return ADER_OK;
+}
+
+ader_status run_faces(ader_ctx *c) {
+  for (size_t p = 0; p < c->P.size(); p++) {
+    ProbState &s = c->P[p];
+    for (int ax = 0; ax < s.D; ax++) {
+      FaceArgs f{};
+      f.ops = s.ops;
+      f.g = s.g;
+      f.trace0 = s.trace[ax][0];
+      f.trace1 = s.trace[ax][1];
+      f.mat = s.mat;
+      f.GL = s.GL[ax];
+      f.GR = s.GR[ax];
+      ader_status st = launch(c, s.ks.face[ax], blocks_for(s.E * s.nf), 0, &f);
+      if (st) return st;
+    }
+  }
+  return ADER_OK;
+}
+
+ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
+  for (size_t p = 0; p < c->P.size(); p++) {
+    ProbState &s = c->P[p];
+    UpdArgs a{};
+    a.ops = s.ops;
+    a.g = s.g;
+    a.ustar = s.ustar;
+    a.dt = (dt_dev ? dt_dev : c->dt) + p;
+    for (int ax = 0; ax < 3; ax++) {
+      a.GL[ax] = s.GL[ax];
+      a.GR[ax] = s.GR[ax];
+    }
+    a.u = u + s.u_off;
+    ader_status st = launch(c, s.ks.update, blocks_for(s.E * s.m * s.nd), 0, &a);
+    if (st) return st;
+  }
+  return ADER_OK;
+}
+
+ader_status run_corrector(ader_ctx *c, double *u, const double *dt_dev) {
+  ader_status st = run_faces(c);
+  return st ? st : run_update(c, u, dt_dev);
+}
+
+ader_status mark(ader_ctx *c) {
+  if (!c->profile) return ADER_OK;
+  hipEvent_t ev;
+  if (!c->ev_pool.empty()) {
+    ev = c->ev_pool.back();
+    c->ev_pool.pop_back();
+  } else {
+    HIP_OR_FAIL(c, hipEventCreate(&ev));
+  }
+  c->ev_used.push_back(ev);
+  HIP_OR_FAIL(c, hipEventRecord(ev, c->stream));
+  return ADER_OK;
+}
+
+ader_status check_flag(ader_ctx *c) {
+  int flag = 0;
+  HIP_OR_FAIL(c, hipMemcpyAsync(&flag, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (flag) {
+    int zero = 0;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->err, &zero, sizeof(int), hipMemcpyHostToDevice, c->stream));
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+    return fail(c, ADER_ERR_NONFINITE, "non-finite or non-physical state (NaN/Inf, rho <= 0 or p <= 0)");
+  }
+  return ADER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ader_version(void) { return "ader-mi355x 0.1 (gfx950)"; }
+
+ader_status ader_stability_alpha(int32_t degree, double *alpha) {
+  if (!alpha || degree < 0) return ADER_ERR_INVALID;
+  if (degree > 7) return ADER_ERR_UNSUPPORTED;
+  *alpha = stability_alpha(degree);
+  return ADER_OK;
+}
+
+ader_status ader_basis(int32_t degree, double *xi, double *w, double *dhat, double *tmat) {
+  if (degree < 0) return ADER_ERR_INVALID;
+  if (degree > 7) return ADER_ERR_UNSUPPORTED;
+  Ops o;
+  if (build_ops(degree, &o)) return ADER_ERR_INVALID;
+  const int n = degree + 1;
+  for (int i = 0; i < n; i++) {
+    if (xi) xi[i] = o.xi[i];
+    if (w) w[i] = o.w[i];
+    for (int j = 0; j < n; j++) {
+      if (dhat) dhat[i * n + j] = o.D[i * kMaxN + j];
+      if (tmat) tmat[i * n + j] = o.T[i * kMaxN + j];
+    }
+  }
+  return ADER_OK;
+}
+
+ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stream, ader_ctx **out) {
+  if (!out) return ADER_ERR_INVALID;
+  *out = nullptr;
+  if (!probs || nprob < 1) {
+    g_create_msg = "probs is NULL or nprob < 1";
+    return ADER_ERR_INVALID;
+  }
+  ader_ctx *c = new ader_ctx();
+  c->stream = (hipStream_t)hip_stream;
+  ader_status st = ADER_OK;
+  auto bail = [&](ader_status s) {
+    g_create_msg = c->msg;  // readable through ader_last_error(NULL)
+    ader_destroy(c);
+    return s;
+  };
+  for (int i = 0; i < nprob; i++)  // argument checks first: they need no device
+    if ((st = validate(c, probs[i], i))) return bail(st);
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    (void)hipGetLastError();
+    c->msg = "no HIP device";
+    return bail(ADER_ERR_DEVICE);
+  }
+  c->P.resize(nprob);
+  int64_t uoff = 0, qoff = 0, moff = 0;
+  for (int i = 0; i < nprob; i++) {
+    const ader_problem &d = probs[i];
+    ProbState &s = c->P[i];
+    s.desc = d;
+    s.D = d.dim;
+    s.N = d.degree;
+    s.ks = kernels_for(d);
+    if (!s.ks.cfl) {
+      c->msg = "no kernels for this configuration";
+      return bail(ADER_ERR_UNSUPPORTED);
+    }
+    s.n = s.ks.n;
+    s.m = s.ks.M;
+    s.nd = s.ks.ND;
+    s.nst = s.ks.NST;
+    s.nf = s.ks.NF;
+    s.E = 1;
+    for (int a = 0; a < 3; a++) {
+      s.g.nel[a] = a < s.D ? d.nelem[a] : 1;
+      s.h[a] = a < s.D ? (d.hi[a] - d.lo[a]) / d.nelem[a] : 1.0;
+      s.g.inv_h[a] = 1.0 / s.h[a];
+      s.E *= s.g.nel[a];
+    }
+    s.g.E = s.E;
+    s.g.gamma = d.gamma;
+    if (build_ops(s.N, &s.ops)) {
+      c->msg = "basis construction failed";
+      return bail(ADER_ERR_INVALID);
+    }
+    s.coef = d.cfl * stability_alpha(s.N);
+    s.sweeps = d.picard_iters > 0 ? d.picard_iters : s.N + 1;
+    s.u_off = uoff;
+    s.u_cnt = s.E * s.m * s.nd;
+    s.q_off = qoff;
+    s.q_cnt = s.E * s.m * s.nst;
+    uoff += s.u_cnt;
+    qoff += s.q_cnt;
+    moff += s.m;
+    const size_t q_bytes = (size_t)s.m * s.nst * sizeof(double);
+    const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
+    if (q_bytes + acc_bytes <= kLdsBytes) {
+      s.acc_lds = true;
+      s.shmem = q_bytes + acc_bytes;
+    } else if (q_bytes <= kLdsBytes) {
+      s.acc_lds = false;
+      s.shmem = q_bytes;
+    } else {
+      c->msg = "problem " + std::to_string(i) + ": space-time DOFs of one element exceed LDS";
+      return bail(ADER_ERR_UNSUPPORTED);
+    }
+    const void *fn = s.acc_lds ? s.ks.pred_lds : s.ks.pred_glob;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s.shmem) !=
+        hipSuccess) {
+      (void)hipGetLastError();
+      c->msg = "cannot reserve " + std::to_string(s.shmem) + " bytes of LDS";
+      return bail(ADER_ERR_UNSUPPORTED);
+    }
+    // device buffers
+    const size_t ub = (size_t)s.u_cnt * sizeof(double);
+    const size_t gb = (size_t)s.E * s.m * s.nf * sizeof(double);
+    if ((st = dalloc(c, (void **)&s.ustar, ub))) return bail(st);
+    for (int a = 0; a < s.D; a++) {
+      for (int sd = 0; sd < 2; sd++)
+        if ((st = dalloc(c, (void **)&s.trace[a][sd], ub))) return bail(st);
+      if ((st = dalloc(c, (void **)&s.GL[a], gb))) return bail(st);
+      if (d.pde == ADER_ELASTIC && (st = dalloc(c, (void **)&s.GR[a], gb))) return bail(st);
+    }
+    if (!s.acc_lds && (st = dalloc(c, (void **)&s.acc, (size_t)s.E * acc_bytes))) return bail(st);
+    if (d.pde == ADER_ELASTIC) {
+      if ((st = dalloc(c, (void **)&s.mat, (size_t)s.E * 3 * sizeof(double)))) return bail(st);
+      if (hipMemcpy(s.mat, d.material, (size_t)s.E * 3 * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+        c->msg = "material upload failed";
+        return bail(ADER_ERR_DEVICE);
+      }
+    }
+  }
+  c->total_u = uoff;
+  c->total_q = qoff;
+  c->total_m = moff;
+  if ((st = dalloc(c, (void **)&c->dt, nprob * sizeof(double)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->t, nprob * sizeof(double)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->tnext, nprob * sizeof(double)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->smax, nprob * sizeof(unsigned long long)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->err, sizeof(int)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->partial, (size_t)kTotBlocks * 9 * sizeof(double)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->sums, (size_t)c->total_m * sizeof(double)))) return bail(st);
+  if (hipMemset(c->dt, 0, nprob * sizeof(double)) != hipSuccess ||
+      hipMemset(c->t, 0, nprob * sizeof(double)) != hipSuccess ||
+      hipMemset(c->tnext, 0, nprob * sizeof(double)) != hipSuccess ||
+      hipMemset(c->smax, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->err, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    c->msg = "initialisation failed";
+    return bail(ADER_ERR_DEVICE);
+  }
+  *out = c;
+  return ADER_OK;
+}
+
+ader_status ader_profile(ader_ctx *c, int32_t enable) {
+  if (!c) return ADER_ERR_INVALID;
+  c->profile = enable != 0;
+  return ADER_OK;
+}
+
+ader_status ader_stage_times(ader_ctx *c, double *ms_host, int64_t *launches_host) {
+  if (!c || !ms_host) return ADER_ERR_INVALID;
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  for (int i = 0; i < 4; i++) {
+    ms_host[i] = 0.0;
+    if (launches_host) launches_host[i] = 0;
+  }
+  for (size_t b = 0; b + 5 <= c->ev_used.size(); b += 5)
+    for (int i = 0; i < 4; i++) {
+      float ms = 0.0f;
+      HIP_OR_FAIL(c, hipEventElapsedTime(&ms, c->ev_used[b + i], c->ev_used[b + i + 1]));
+      ms_host[i] += ms;
+      if (launches_host) launches_host[i] += 1;
+    }
+  for (hipEvent_t e : c->ev_used) c->ev_pool.push_back(e);
+  c->ev_used.clear();
+  return ADER_OK;
+}
+
+ader_status ader_destroy(ader_ctx *c) {
+  if (!c) return ADER_OK;
+  if (!c->allocs.empty() || !c->ev_used.empty() || !c->ev_pool.empty()) (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev_used) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (void *p : c->allocs) (void)hipFree(p);
+  delete c;
+  return ADER_OK;
+}
+
+ader_status ader_layout(const ader_ctx *c, int32_t prob, int64_t *offset, int64_t *count) {
+  if (!c || prob < 0 || prob >= (int32_t)c->P.size()) return ADER_ERR_INVALID;
+  if (offset) *offset = c->P[prob].u_off;
+  if (count) *count = c->P[prob].u_cnt;
+  return ADER_OK;
+}
+
+ader_status ader_qhat_layout(const ader_ctx *c, int32_t prob, int64_t *offset, int64_t *count) {
+  if (!c || prob < 0 || prob >= (int32_t)c->P.size()) return ADER_ERR_INVALID;
+  if (offset) *offset = c->P[prob].q_off;
+  if (count) *count = c->P[prob].q_cnt;
+  return ADER_OK;
+}
+
+ader_status ader_state_size(const ader_ctx *c, int64_t *count) {
+  if (!c || !count) return ADER_ERR_INVALID;
+  *count = c->total_u;
+  return ADER_OK;
+}
+
+ader_status ader_cfl_dt(ader_ctx *c, const double *u, double *dt_host) {
+  if (!c) return ADER_ERR_INVALID;
+  if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  ader_status st = run_cfl(c, u, nullptr);
+  if (st || !dt_host) return st;
+  HIP_OR_FAIL(c, hipMemcpyAsync(dt_host, c->dt, c->P.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  return check_flag(c);
+}
+
+ader_status ader_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat_out) {
+  if (!c) return ADER_ERR_INVALID;
+  if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  return run_predictor(c, u, dt_dev, qhat_out);
+}
+
+ader_status ader_corrector(ader_ctx *c, double *u, const double *dt_dev) {
+  if (!c) return ADER_ERR_INVALID;
+  if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  return run_corrector(c, u, dt_dev);
+}
+
+ader_status ader_step(ader_ctx *c, double *u, const double *t_end_host) {
+  if (!c) return ADER_ERR_INVALID;
+  if (!u || !t_end_host) return fail(c, ADER_ERR_INVALID, "u and t_end must not be NULL");
+  ader_status st;
+  if ((st = mark(c)) || (st = run_cfl(c, u, t_end_host))) return st;
+  if ((st = mark(c)) || (st = run_predictor(c, u, nullptr, nullptr))) return st;
+  if ((st = mark(c)) || (st = run_faces(c))) return st;
+  if ((st = mark(c)) || (st = run_update(c, u, nullptr))) return st;
+  if ((st = mark(c))) return st;
+  const int np = (int)c->P.size();
+  hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->stream, c->t, c->tnext, np);
+  HIP_OR_FAIL(c, hipGetLastError());
+  return ADER_OK;
+}
+
+ader_status ader_time(ader_ctx *c, double *t_host) {
+  if (!c || !t_host) return ADER_ERR_INVALID;
+  HIP_OR_FAIL(c, hipMemcpyAsync(t_host, c->t, c->P.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  return check_flag(c);
+}
+
+ader_status ader_last_dt(ader_ctx *c, double *dt_host) {
+  if (!c || !dt_host) return ADER_ERR_INVALID;
+  HIP_OR_FAIL(c, hipMemcpyAsync(dt_host, c->dt, c->P.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                c->stream));
+  return check_flag(c);
+}
+
+ader_status ader_set_time(ader_ctx *c, const double *t_host) {
+  if (!c || !t_host) return ADER_ERR_INVALID;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->t, t_host, c->P.size() * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+ader_status ader_totals(ader_ctx *c, const double *u, double *sums_host) {
+  if (!c || !sums_host) return ADER_ERR_INVALID;
+  if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  int64_t moff = 0;
+  for (size_t p = 0; p < c->P.size(); p++) {
+    ProbState &s = c->P[p];
+    double vol = 1.0;
+    for (int a = 0; a < s.D; a++) vol *= s.h[a];
+    hipLaunchKernelGGL(k_totals_partial, dim3(kTotBlocks), dim3(kBlock), 0, c->stream, u + s.u_off,
+                       s.E, s.m, s.nd, s.n, s.D, s.ops, vol, c->partial);
+    hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, c->stream, c->partial, kTotBlocks, s.m,
+                       c->sums + moff);
+    HIP_OR_FAIL(c, hipGetLastError());
+    moff += s.m;
+  }
+  HIP_OR_FAIL(c, hipMemcpyAsync(sums_host, c->sums, (size_t)c->total_m * sizeof(double),
+                                hipMemcpyDeviceToHost, c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+const char *ader_last_error(const ader_ctx *c) {
+  if (!c) return g_create_msg.c_str();
+  return c->msg.c_str();
+}
+
+}  // extern "C"

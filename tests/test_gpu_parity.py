@@ -1,0 +1,281 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle.
+
+Both sides receive the same seeded inputs from paper_1808_03788_amd.inputs;
+the library is called through the C ABI (ctypes binding).  FP64 path
+tolerance: 1e-12 relative L2 per variable (the max over variables).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1808_03788_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_03788_amd import ader
+    ader.lib()
+    return ader
+
+
+def gpu_run(A, prob, u0, steps, t_end=1e9):
+    import torch
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    for _ in range(steps):
+        ctx.step(u, t_end)
+    torch.cuda.synchronize()
+    t = ctx.time()[0]
+    out = ctx.download(u)[0]
+    ctx.close()
+    return out, t
+
+
+def orc_run(orc, prob, u0, steps, t_end=1e9):
+    u, t = u0, 0.0
+    for _ in range(steps):
+        u, t, _ = orc.step(prob, u, t, t_end)
+    return u, t
+
+
+def check(prob, a, ref, tol=TOL64, what=""):
+    err = I.rel_l2(prob, a, ref)
+    say(f"  {what} rel_l2={err:.3e} linf={I.linf(a, ref):.3e}")
+    assert err <= tol, (what, err)
+
+
+CASES = [
+    ("vortex2d_N3_16", lambda: I.vortex_problem(nel=16, N=3), I.isentropic_vortex, 8),
+    ("euler3d_N4_5x6x7", lambda: I.Problem(dim=3, N=4, nel=(5, 6, 7), lo=(0, 0, 0), hi=(1, 1.2, 1.4)),
+     lambda p: I.density_wave(p), 5),
+    ("euler3d_N3_ragged", lambda: I.Problem(dim=3, N=3, nel=(9, 3, 2), lo=(0, 0, 0), hi=(1, 1, 1)),
+     lambda p: I.fourier_modes(p), 4),
+    ("elastic_N2_6x5x4", lambda: I.elastic_problem(nel=4, N=2), lambda p: I.stress_pulse(p, width=0.2), 5),
+    ("elastic_N5_acc_hbm", lambda: I.elastic_problem(nel=3, N=5), lambda p: I.stress_pulse(p, width=0.25), 3),
+]
+
+
+@pytest.mark.parametrize("name,mk,init,steps", CASES, ids=[c[0] for c in CASES])
+def test_steps_parity(A, orc, name, mk, init, steps):
+    prob = mk()
+    u0 = init(prob)
+    say(f"[parity] {name} E={prob.E} N={prob.N} steps={steps}")
+    ug, tg = gpu_run(A, prob, u0, steps)
+    uo, to = orc_run(orc, prob, u0, steps)
+    assert abs(tg - to) <= 1e-14 * max(1.0, abs(to))
+    check(prob, ug, uo, what=name)
+
+
+@pytest.mark.parametrize("N", range(0, 8))
+def test_every_degree_2d(A, orc, N):
+    prob = I.vortex_problem(nel=5, N=N)
+    u0 = I.isentropic_vortex(prob)
+    say(f"[parity] 2-D Euler degree {N}")
+    ug, _ = gpu_run(A, prob, u0, 3)
+    uo, _ = orc_run(orc, prob, u0, 3)
+    check(prob, ug, uo, what=f"N={N}")
+
+
+@pytest.mark.parametrize("N", range(0, 6))
+def test_every_degree_3d(A, orc, N):
+    prob = I.Problem(dim=3, N=N, nel=(3, 2, 4), lo=(0, 0, 0), hi=(1, 1, 1))
+    u0 = I.density_wave(prob)
+    say(f"[parity] 3-D Euler degree {N}")
+    ug, _ = gpu_run(A, prob, u0, 2)
+    uo, _ = orc_run(orc, prob, u0, 2)
+    check(prob, ug, uo, what=f"N={N}")
+
+
+def test_predictor_qhat_parity(A, orc):
+    import torch
+    for prob, u0 in [
+        (I.Problem(dim=3, N=4, nel=(3, 4, 5), lo=(0, 0, 0), hi=(1, 1, 1)), None),
+        (I.elastic_problem(nel=3, N=3), None),
+    ]:
+        u0 = I.density_wave(prob) if prob.pde == "euler" else I.stress_pulse(prob, width=0.2)
+        say(f"[parity] predictor {prob.pde} N={prob.N}")
+        dt = orc.cfl_dt(prob, u0)
+        ctx = A.Context([prob])
+        u = ctx.upload([u0])
+        q = ctx.predictor(u, dt=[dt], qhat=True)
+        torch.cuda.synchronize()
+        qg = ctx.qhat_views(q)[0]
+        qo = orc.predictor(prob, u0, dt)
+        err = np.abs(qg - qo).max() / np.abs(qo).max()
+        say(f"  qhat max rel err {err:.3e}")
+        assert err < 1e-13
+        ctx.close()
+
+
+def test_cfl_dt_parity(A, orc):
+    for prob, u0 in [(I.vortex_problem(nel=7, N=2), None), (I.elastic_problem(nel=4, N=1), None),
+                     (I.density_wave_problem(nel=5, N=3), None)]:
+        u0 = (I.isentropic_vortex(prob) if prob.dim == 2 else
+              I.stress_pulse(prob) if prob.pde == "elastic" else I.density_wave(prob))
+        ctx = A.Context([prob])
+        dt = ctx.cfl_dt(ctx.upload([u0]))[0]
+        ref = orc.cfl_dt(prob, u0)
+        say(f"[parity] cfl {prob.pde} d={prob.dim}: {dt!r} vs {ref!r}")
+        assert abs(dt - ref) <= 1e-15 * ref
+        ctx.close()
+
+
+def test_full_run_vortex_to_t1(A, orc):
+    """The first workload (16x16, N=3, CFL 0.9) run to t = 1 on both sides."""
+    prob = I.vortex_problem(nel=16, N=3)
+    u0 = I.isentropic_vortex(prob)
+    import torch
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    steps = 0
+    while ctx.time()[0] < 1.0 and steps < 1000:
+        ctx.step(u, 1.0)
+        steps += 1
+    torch.cuda.synchronize()
+    ug = ctx.download(u)[0]
+    uo, to, so = orc.run(prob, u0, 0.0, 1.0)
+    say(f"[parity] vortex to t=1: {steps} steps (oracle {so})")
+    assert steps == so and ctx.time()[0] == 1.0
+    check(prob, ug, uo, what="vortex t=1")
+    err_exact = I.l2_per_var(prob, ug - I.isentropic_vortex(prob, 1.0))
+    say(f"  L2 error vs exact (rho) {err_exact[0]:.3e}")
+    ctx.close()
+
+
+def test_full_size_density_wave_sampled(A, orc):
+    """64^3, N=4 (the benchmark workload): one step on the GPU; 12 sampled
+    elements checked against the oracle run on their 3x3x3 periodic
+    neighbourhood with the same dt (the update of the centre element only
+    depends on its face neighbours)."""
+    import torch
+    prob = I.density_wave_problem(nel=64, N=4)
+    u0 = I.density_wave(prob)
+    say("[parity] 64^3 N=4 sampled")
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    ctx.step(u, 1e9)
+    torch.cuda.synchronize()
+    dt = ctx.last_dt()[0]
+    dto = orc.cfl_dt(prob, u0)
+    assert abs(dt - dto) <= 1e-15 * dto
+    ug = u.view(prob.E, prob.m, prob.nd)
+    rng = np.random.default_rng(7)
+    n = 64
+    picks = [(0, 0, 0), (63, 63, 63), (0, 63, 31)] + [tuple(rng.integers(0, n, 3)) for _ in range(9)]
+    for (ix, iy, iz) in picks:
+        ids = [((ix + dx) % n) + n * (((iy + dy) % n) + n * ((iz + dz) % n))
+               for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+        sub = I.density_wave_problem(nel=3, N=4)
+        sub.hi = (3 / 64, 3 / 64, 3 / 64)
+        usub = u0[ids]
+        q = orc.predictor(sub, usub, dt)
+        un = orc.corrector(sub, usub, q, dt)
+        e = ids[13]
+        got = ug[e].cpu().numpy()
+        err = np.abs(got - un[13]).max() / np.abs(un[13]).max()
+        assert err < 1e-13, ((ix, iy, iz), err)
+    say(f"  {len(picks)} elements within 1e-13")
+    ctx.close()
+
+
+def test_conservation_and_freestream(A, orc):
+    import torch
+    prob = I.density_wave_problem(nel=6, N=3)
+    u0 = I.density_wave(prob)
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    s0 = ctx.totals(u)
+    so = orc.totals(prob, u0)
+    np.testing.assert_allclose(s0, so, rtol=1e-14, atol=1e-14)
+    for _ in range(5):
+        ctx.step(u, 1e9)
+    s1 = ctx.totals(u)
+    say(f"[gpu] conservation drift {np.abs(s1 - s0).max():.2e}")
+    assert np.abs(s1 - s0).max() <= 1e-13 * np.abs(s0).max()
+    uf = I.uniform_state(prob)
+    u = ctx.upload([uf])
+    ctx.step(u, 1e9)
+    torch.cuda.synchronize()
+    assert np.abs(ctx.download(u)[0] - uf).max() < 1e-14 * np.abs(uf).max()
+    ctx.close()
+
+
+def test_nonfinite_is_reported(A):
+    import torch
+    prob = I.density_wave_problem(nel=3, N=2)
+    u0 = I.density_wave(prob)
+    u0[4, 0, 5] = np.nan
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    with pytest.raises(A.AderError) as e:
+        ctx.cfl_dt(u)
+    assert e.value.status == A.ADER_ERR_NONFINITE
+    u0[4, 0, 5] = -1.0          # negative density
+    u = ctx.upload([u0])
+    ctx.step(u, 1.0)            # asynchronous: latched
+    with pytest.raises(A.AderError) as e:
+        ctx.time()
+    assert e.value.status == A.ADER_ERR_NONFINITE
+    assert ctx.last_dt()[0] == 0.0
+    ctx.close()
+
+
+def test_deterministic_and_resume(A):
+    import torch
+    prob = I.density_wave_problem(nel=4, N=3)
+    u0 = I.density_wave(prob)
+    runs = []
+    for _ in range(2):
+        ctx = A.Context([prob])
+        u = ctx.upload([u0])
+        for _ in range(6):
+            ctx.step(u, 1e9)
+        torch.cuda.synchronize()
+        runs.append((ctx.download(u)[0], ctx.time()[0]))
+        ctx.close()
+    assert np.array_equal(runs[0][0], runs[1][0]) and runs[0][1] == runs[1][1]
+    ctx = A.Context([prob])
+    u = ctx.upload([u0])
+    for _ in range(3):
+        ctx.step(u, 1e9)
+    saved, t = ctx.download(u)[0], ctx.time()
+    ctx.close()
+    ctx = A.Context([prob])
+    ctx.set_time(t)
+    u = ctx.upload([saved])
+    for _ in range(3):
+        ctx.step(u, 1e9)
+    torch.cuda.synchronize()
+    assert np.array_equal(ctx.download(u)[0], runs[0][0]) and ctx.time()[0] == runs[0][1]
+    ctx.close()
+
+
+def test_multiple_problems_one_context(A, orc):
+    import torch
+    probs = [I.vortex_problem(nel=4, N=2), I.density_wave_problem(nel=3, N=3),
+             I.elastic_problem(nel=2, N=2)]
+    inits = [I.isentropic_vortex(probs[0]), I.density_wave(probs[1]), I.stress_pulse(probs[2], width=0.3)]
+    ctx = A.Context(probs)
+    u = ctx.upload(inits)
+    t_end = [0.3, 1e9, 1e9]
+    for _ in range(3):
+        ctx.step(u, t_end)
+    torch.cuda.synchronize()
+    outs = ctx.download(u)
+    for p, u0, ug, te in zip(probs, inits, outs, t_end):
+        uo, _ = orc_run(orc, p, u0, 3, te)
+        check(p, ug, uo, what=f"multi {p.pde} d={p.dim}")
+    ctx.close()
