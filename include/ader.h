@@ -152,6 +152,17 @@ ader_status ader_totals(ader_ctx *ctx, const double *u, double *sums_host);
 ader_status ader_profile(ader_ctx *ctx, int32_t enable);
 ader_status ader_stage_times(ader_ctx *ctx, double *ms_host, int64_t *launches_host);
 
+/* Human-readable description of the kernels chosen for problem `prob`
+ * (predictor variant, workgroup size, LDS bytes, how it was selected), as
+ * a NUL-terminated string of at most len bytes in the host buffer buf.
+ * The predictor variant is picked at ader_create: the implementations of
+ * the problem's precision (VALU or MFMA contractions, two workgroup sizes)
+ * are timed on a uniform state of up to 32768 elements and the fastest is
+ * kept, cached per configuration for the process.  Environment:
+ * ADER_AUTOTUNE=0 keeps the first candidate; ADER_VARIANT=<name> forces one
+ * (names as printed here). */
+ader_status ader_describe(const ader_ctx *ctx, int32_t prob, char *buf, int32_t len);
+
 /* Message of the last failing call on this context (never NULL); with
  * ctx = NULL, the message of the last failed ader_create on this thread. */
 const char *ader_last_error(const ader_ctx *ctx);

@@ -27,6 +27,7 @@ EXPORTS = [
     "ader_predictor", "ader_qhat_layout", "ader_corrector", "ader_step", "ader_time",
     "ader_set_time", "ader_last_dt", "ader_totals", "ader_last_error",
     "ader_stability_alpha", "ader_basis", "ader_version", "ader_profile", "ader_stage_times",
+    "ader_describe",
 ]
 
 
@@ -78,6 +79,7 @@ def lib():
         L.ader_version.restype = C.c_char_p
         L.ader_profile.argtypes = [_VP, C.c_int32]
         L.ader_stage_times.argtypes = [_VP, _DP, C.POINTER(C.c_int64)]
+        L.ader_describe.argtypes = [_VP, C.c_int32, C.c_char_p, C.c_int32]
         for name in EXPORTS:
             if name not in ("ader_last_error", "ader_version"):
                 getattr(L, name).restype = C.c_int
@@ -235,6 +237,12 @@ def ader_stage_times(ctx: int):
     cnt = (C.c_int64 * 4)()
     _check(lib().ader_stage_times(_VP(ctx), ms.ctypes.data_as(_DP), cnt), ctx)
     return {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(4)}
+
+
+def ader_describe(ctx: int, prob: int = 0) -> str:
+    buf = C.create_string_buffer(512)
+    _check(lib().ader_describe(_VP(ctx), prob, buf, 512), ctx)
+    return buf.value.decode()
 
 
 def ader_last_error(ctx: Optional[int]) -> str:

@@ -2,6 +2,8 @@
 // degree N and PDE system.  One workgroup owns one element in the predictor;
 // the face and update kernels are one thread per face node / per DOF.
 #pragma once
+#include <type_traits>
+
 #include "ader_common.hpp"
 
 namespace ader {
@@ -23,10 +25,15 @@ struct Elastic {
   static constexpr bool kElastic = true;
 };
 
+// 1/x: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32,
+// where the Picard sweeps are later corrected by an FP64 sweep.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Flux F_A(q) of the Euler equations; p = (gamma-1)(rho E - |rho v|^2/(2 rho)).
 template <int D, int A, typename R>
 __device__ __forceinline__ void euler_flux(const R *q, R gm1, R *F) {
-  const R ir = R(1) / q[0];
+  const R ir = recip(q[0]);
   R ke = R(0);
 #pragma unroll
   for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
@@ -46,6 +53,17 @@ __device__ __forceinline__ double euler_pressure(const double *q, double gamma) 
 #pragma unroll
   for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
   return (gamma - 1.0) * (q[D + 1] - 0.5 * ke / q[0]);
+}
+
+// |v_A| + c with one division: 1/rho, then products.
+template <int D, int A>
+__device__ __forceinline__ double euler_speed(const double *q, double gamma) {
+  const double ir = 1.0 / q[0];
+  double ke = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
+  const double p = (gamma - 1.0) * (q[D + 1] - 0.5 * ke * ir);
+  return fabs(q[1 + A] * ir) + sqrt(gamma * p * ir);
 }
 
 // Index of stress component s_{iA} in the elastic state vector.
@@ -72,29 +90,29 @@ __device__ __forceinline__ void elastic_bg(const R *g, R irho, R lam, R mu, R *o
   out[8] = -mu * ((A == 0 ? g[2] : R(0)) + (A == 2 ? g[0] : R(0)));
 }
 
-__device__ __forceinline__ int64_t neighbour(int64_t e, int A, int dir, const int *nel) {
-  int64_t ix = e % nel[0];
-  int64_t r = e / nel[0];
-  int64_t iy = r % nel[1];
-  int64_t iz = r / nel[1];
-  if (A == 0) ix = (ix + dir + nel[0]) % nel[0];
-  if (A == 1) iy = (iy + dir + nel[1]) % nel[1];
-  if (A == 2) iz = (iz + dir + nel[2]) % nel[2];
-  return ix + (int64_t)nel[0] * (iy + (int64_t)nel[1] * iz);
-}
-
 // ------------------------------------------------------------ predictor
+
+// Precision modes of the predictor's Picard sweeps.
+enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
+
+// Float copies of the sweep operators (the FP32/BF16 sweeps use these).
+struct OpsF {
+  float D[kMaxN * kMaxN];
+  float T[kMaxN * kMaxN];
+};
 
 struct PredArgs {
   Ops ops;
+  OpsF opsf;
   Geom g;
   const double *u;      // [E][M][ND]
   const double *dt;     // device scalar
   const double *mat;    // elastic: [E][3]
   double *ustar;        // [E][M][ND]  u + dt * volume terms
-  double *trace[3][2];  // [E][M][n][ND/n] per axis and side (0: x_A = 0, 1: x_A = 1)
+  void *trace[3][2];    // [E][M][n][ND/n] per axis and side (0: x_A = 0, 1: x_A = 1);
+                        // double for FP64, float for the mixed modes
   double *qhat;         // optional [E][M][n][ND]
-  double *acc_glob;     // accumulator when it does not fit in LDS: [E][M][max(NST,2ND)]
+  double *acc_glob;     // FP64 accumulator when it does not fit in LDS: [E][M][ACC]
   int sweeps;
 };
 
@@ -104,55 +122,113 @@ struct Shape {
   static constexpr int ND = ipow(n, D);
   static constexpr int NST = ND * n;
   static constexpr int NF = ND / n;   // face nodes
-  static constexpr int ACC = (NST > 2 * ND) ? NST : 2 * ND;
+  static constexpr int ACC = (NST > D * ND) ? NST : D * ND;  // also holds D*M*ND output scratch
 };
 
-// Collocated right-hand side along axis A for all lines of the element:
+// LDS bytes of the predictor: region A holds the space-time DOFs q in the
+// sweep precision (and, in the mixed modes, the output scratch); region R
+// the right-hand-side accumulator (and, in the mixed modes, the FP64 final
+// iterate).
+__host__ __device__ constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+template <int D, int N, int M, int PREC>
+struct PredLds {
+  using S = Shape<D, N>;
+  // region R starts 256-byte aligned so that its FP64 accesses stay aligned
+  static constexpr size_t A = round256(
+      PREC == kFP64 ? (size_t)M * S::NST * 8
+                    : ((size_t)M * S::NST * 4 > (size_t)D * M * S::ND * 8 ? (size_t)M * S::NST * 4
+                                                                            : (size_t)D * M * S::ND * 8));
+  static constexpr size_t R = round256(PREC == kFP64 ? (size_t)M * S::ACC * 8 : (size_t)M * S::NST * 8);
+};
+
+// Threads per workgroup of the predictor: the number of lines of one axis
+// phase (n^D) rounded up to whole wavefronts, times a tuning factor (1 or
+// 2), at most 256.
+__host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
+  return (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > 256
+             ? 256
+             : (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor;
+}
+
+template <typename T>
+__device__ __forceinline__ T opD(const PredArgs &P, int i);
+template <>
+__device__ __forceinline__ double opD<double>(const PredArgs &P, int i) { return P.ops.D[i]; }
+template <>
+__device__ __forceinline__ float opD<float>(const PredArgs &P, int i) { return P.opsf.D[i]; }
+template <typename T>
+__device__ __forceinline__ T opT(const PredArgs &P, int i);
+template <>
+__device__ __forceinline__ double opT<double>(const PredArgs &P, int i) { return P.ops.T[i]; }
+template <>
+__device__ __forceinline__ float opT<float>(const PredArgs &P, int i) { return P.opsf.T[i]; }
+
+// Round to the nearest bfloat16 (ties to even), kept in a float register.
+__device__ __forceinline__ float round_bf16(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7fffu + ((b >> 16) & 1u);
+  return __uint_as_float(b & 0xffff0000u);
+}
+
+// Collocated right-hand side along axis A for all lines of the element, in
+// arithmetic T, reading q stored as TQ:
 //   R -= (1/h_A) Dhat_A F_A(q)           (Euler)
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
-// Lines are enumerated over (l0, the other spatial indices).
-template <int D, int N, class PDE, int A>
-__device__ __forceinline__ void rhs_axis(const PredArgs &P, const double *sq, double *sacc,
-                                         double irho, double lam, double mu) {
+// Lines are enumerated over (l0, the other spatial indices).  With kRoundBF
+// the contraction inputs are rounded to bfloat16.
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS>
+__device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sacc, T irho, T lam,
+                                         T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
-  const double ih = P.g.inv_h[A];
-  for (int L = threadIdx.x; L < NST / n; L += kBlock) {
+  const T ih = (T)P.g.inv_h[A];
+  for (int L = threadIdx.x; L < NST / n; L += BS) {
     const int l0 = L / NF, r = L - l0 * NF;
     const int lo = r % ST, hi = r / ST;
     const int base = l0 * ND + lo + hi * ST * n;
-    double qv[n][M];
+    T qv[n][M];
 #pragma unroll
     for (int j = 0; j < n; j++)
 #pragma unroll
-      for (int v = 0; v < M; v++) qv[j][v] = sq[v * NST + base + j * ST];
-    double out[n][M];
+      for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * NST + base + j * ST];
+    T out[n][M];
     if constexpr (!PDE::kElastic) {
-      double F[n][M];
+      T F[n][M];
 #pragma unroll
-      for (int j = 0; j < n; j++) euler_flux<D, A>(qv[j], P.g.gamma - 1.0, F[j]);
+      for (int j = 0; j < n; j++) {
+        euler_flux<D, A, T>(qv[j], (T)(P.g.gamma - 1.0), F[j]);
+        if constexpr (kRoundBF)
+#pragma unroll
+          for (int v = 0; v < M; v++) F[j][v] = round_bf16(F[j][v]);
+      }
 #pragma unroll
       for (int k = 0; k < n; k++)
 #pragma unroll
         for (int v = 0; v < M; v++) {
-          double s = 0.0;
+          T s = T(0);
 #pragma unroll
-          for (int j = 0; j < n; j++) s += P.ops.D[k * kMaxN + j] * F[j][v];
+          for (int j = 0; j < n; j++) s += opD<T>(P, k * kMaxN + j) * F[j][v];
           out[k][v] = -s * ih;
         }
     } else {
+      if constexpr (kRoundBF)
+#pragma unroll
+        for (int j = 0; j < n; j++)
+#pragma unroll
+          for (int v = 0; v < M; v++) qv[j][v] = round_bf16(qv[j][v]);
 #pragma unroll
       for (int k = 0; k < n; k++) {
-        double gk[M], bg[M];
+        T gk[M], bg[M];
 #pragma unroll
         for (int v = 0; v < M; v++) {
-          double s = 0.0;
+          T s = T(0);
 #pragma unroll
-          for (int j = 0; j < n; j++) s += P.ops.D[k * kMaxN + j] * qv[j][v];
+          for (int j = 0; j < n; j++) s += opD<T>(P, k * kMaxN + j) * qv[j][v];
           gk[v] = s;
         }
-        elastic_bg<A>(gk, irho, lam, mu, bg);
+        elastic_bg<A, T>(gk, irho, lam, mu, bg);
 #pragma unroll
         for (int v = 0; v < M; v++) out[k][v] = -bg[v] * ih;
       }
@@ -168,96 +244,314 @@ __device__ __forceinline__ void rhs_axis(const PredArgs &P, const double *sq, do
   }
 }
 
-// Euler volume term along axis A from the time-integrated flux:
-//   V += (1/h_A) Vop_A [ sum_l0 w_l0 F_A(q(l0)) ]
-template <int D, int N, class PDE, int A>
-__device__ __forceinline__ void volume_axis_euler(const PredArgs &P, const double *sq, double *sV) {
+// Number of (v,k) time lines each thread owns in the time phase.
+template <int D, int N, int M, int BS>
+struct TimeItems {
+  static constexpr int value = (M * ipow(N + 1, D) + BS - 1) / BS;
+};
+
+// Time contraction q(l0,k) = u(k) + dt sum_j0 T[l0][j0] R(j0,k), in arithmetic
+// T, writing q as TO (may alias R: every thread reads its whole time line
+// before writing it back).  Thread tid owns the time lines tid + r*BS, whose
+// u values it keeps in ureg[r] across sweeps.
+template <int D, int N, class PDE, typename T, typename TO, int BS>
+__device__ __forceinline__ void time_phase(const PredArgs &P, const T *sacc, TO *qout,
+                                           const double *ureg, T dt) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
-  constexpr int ST = ipow(n, A);
-  const double ih = P.g.inv_h[A];
-  for (int L = threadIdx.x; L < NF; L += kBlock) {
-    const int lo = L % ST, hi = L / ST;
-    const int base = lo + hi * ST * n;
-    double Fb[n][M];
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
 #pragma unroll
-    for (int j = 0; j < n; j++)
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    if (i < M * ND) {
+      const int v = i / ND, k = i - v * ND;
+      T rr[n];
 #pragma unroll
-      for (int v = 0; v < M; v++) Fb[j][v] = 0.0;
-    for (int l0 = 0; l0 < n; l0++) {
-      const double wl = P.ops.w[l0];
+      for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
+      const T u0 = (T)ureg[r];
 #pragma unroll
-      for (int j = 0; j < n; j++) {
-        double qv[M], F[M];
+      for (int l = 0; l < n; l++) {
+        T a = T(0);
 #pragma unroll
-        for (int v = 0; v < M; v++) qv[v] = sq[v * NST + l0 * ND + base + j * ST];
-        euler_flux<D, A>(qv, P.g.gamma - 1.0, F);
-#pragma unroll
-        for (int v = 0; v < M; v++) Fb[j][v] += wl * F[v];
+        for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
+        qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
       }
     }
-#pragma unroll
-    for (int k = 0; k < n; k++)
-#pragma unroll
-      for (int v = 0; v < M; v++) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < n; j++) s += P.ops.V[k * kMaxN + j] * Fb[j][v];
-        const int idx = v * ND + base + k * ST;
-        if (A == 0) sV[idx] = s * ih;
-        else sV[idx] += s * ih;
-      }
   }
 }
 
-// Elastic volume term along axis A: V -= (1/h_A) B_A Dhat_A qbar,
-// qbar = sum_l0 w_l0 q(l0) (B is constant in the element).
-template <int D, int N, int A>
-__device__ __forceinline__ void volume_axis_elastic(const PredArgs &P, const double *sQ, double *sV,
-                                                    double irho, double lam, double mu) {
+// One Picard sweep: R(q) over all axes, then the time contraction.
+template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS>
+__device__ __forceinline__ void picard_sweep(const PredArgs &P, const TQ *sq, T *sacc, TO *qout,
+                                             const double *ureg, T dt, T irho, T lam, T mu) {
+  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+  __syncthreads();
+  if constexpr (D > 1) {
+    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    __syncthreads();
+  }
+  if constexpr (D > 2) {
+    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    __syncthreads();
+  }
+  time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- MFMA sweep
+//
+// FP32 Picard sweep whose operator contractions run on v_mfma_f32_4x4x1_16b:
+// 16 independent 4x4 outer-product blocks per instruction.  Lane 4b+i of a
+// wavefront supplies row i of block b (A operand), lane 4b+j supplies column
+// j (B operand); the 4x4 result of block b lands in lane 4b+j, register i.
+// Every lane owns one line (n nodes of one axis, all M variables) and feeds
+// its own value at node j as B; the A operand of lane 4b+i is the operator
+// entry Op[4c+i][j].  One instruction per node j (K = 1, no padding) and per
+// group c of four output nodes thus leaves out[k = 4c+i] = sum_j Op[k][j] X[j]
+// of the lane's own line in register i: no data moves between lanes.
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <int D, int N>
+__device__ __forceinline__ int line_base(int line, int ST) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = 9, ND = S::ND, NF = S::NF;
+  const int l0 = line / S::NF, r = line - l0 * S::NF;
+  return l0 * S::ND + (r % ST) + (r / ST) * ST * S::n;
+}
+
+template <int D, int N, class PDE, int A, int BS>
+__device__ __forceinline__ void rhs_axis_mfma(const PredArgs &P, const float *sq, float *sacc,
+                                              const float (&Da)[2][N + 1], float irho, float lam,
+                                              float mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, NST = S::NST;
   constexpr int ST = ipow(n, A);
-  const double ih = P.g.inv_h[A];
-  for (int L = threadIdx.x; L < NF; L += kBlock) {
-    const int lo = L % ST, hi = L / ST;
-    const int base = lo + hi * ST * n;
-    double qv[n][M];
+  constexpr int NL = NST / n;
+  constexpr int NC = (n + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float ih = (float)P.g.inv_h[A];
+  for (int L0 = wave * 64; L0 < NL; L0 += BS) {
+    const bool own = L0 + lane < NL;
+    const int base = line_base<D, N>(own ? L0 + lane : L0, ST);
+    float X[n][M];
+#pragma unroll
+    for (int j = 0; j < n; j++) {
+      float q[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) q[v] = sq[v * NST + base + j * ST];
+      if constexpr (!PDE::kElastic) euler_flux<D, A, float>(q, (float)(P.g.gamma - 1.0), X[j]);
+      else
+#pragma unroll
+        for (int v = 0; v < M; v++) X[j][v] = q[v];
+    }
+    f4v acc[NC][M];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+      for (int v = 0; v < M; v++) acc[c][v] = f4v{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int j = 0; j < n; j++)
 #pragma unroll
-      for (int v = 0; v < M; v++) qv[j][v] = sQ[v * ND + base + j * ST];
+      for (int c = 0; c < NC; c++)
 #pragma unroll
-    for (int k = 0; k < n; k++) {
-      double gk[M], bg[M];
+        for (int v = 0; v < M; v++)
+          acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(Da[c][j], X[j][v], acc[c][v], 0, 0, 0);
+    if (own) {
+#pragma unroll
+      for (int k = 0; k < n; k++) {
+        float out[M];
+        if constexpr (!PDE::kElastic) {
+#pragma unroll
+          for (int v = 0; v < M; v++) out[v] = -acc[k / 4][v][k % 4] * ih;
+        } else {
+          float g[M], bg[M];
+#pragma unroll
+          for (int v = 0; v < M; v++) g[v] = acc[k / 4][v][k % 4];
+          elastic_bg<A, float>(g, irho, lam, mu, bg);
+#pragma unroll
+          for (int v = 0; v < M; v++) out[v] = -bg[v] * ih;
+        }
+#pragma unroll
+        for (int v = 0; v < M; v++) {
+          const int idx = v * NST + base + k * ST;
+          if (A == 0) sacc[idx] = out[v];
+          else sacc[idx] += out[v];
+        }
+      }
+    }
+  }
+}
+
+// Time contraction on MFMA: lane owns the time line (v,k).  One extra
+// instruction with A = 1 and B = u seeds every output with u, so the result
+// is q(l) = u + sum_j T[l][j] (dt R(j)).
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void time_phase_mfma(const float *sacc, float *sq, const double *ureg, float dt,
+                                                const float (&Ta)[2][N + 1]) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NTL = M * ND;
+  constexpr int NC = (n + 3) / 4;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int T0 = wave * 64 + r * BS;
+    if (T0 >= NTL) break;  // uniform over the wavefront
+    const bool own = T0 + lane < NTL;
+    const int Lt = own ? T0 + lane : T0;
+    const int v = Lt / ND, k = Lt - v * ND;
+    float b[n];
+#pragma unroll
+    for (int j = 0; j < n; j++) b[j] = dt * sacc[v * NST + j * ND + k];
+    const float u0 = (float)ureg[r];
+    f4v acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; c++)
+      acc[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(1.0f, u0, f4v{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < n; j++)
+#pragma unroll
+      for (int c = 0; c < NC; c++) acc[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ta[c][j], b[j], acc[c], 0, 0, 0);
+    if (own)
+#pragma unroll
+      for (int l = 0; l < n; l++) sq[v * NST + l * ND + k] = acc[l / 4][l % 4];
+  }
+}
+
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void picard_sweep_mfma(const PredArgs &P, float *sq, float *sacc, const double *ureg,
+                                                  float dt, float irho, float lam, float mu,
+                                                  const float (&Da)[2][N + 1], const float (&Ta)[2][N + 1]) {
+  rhs_axis_mfma<D, N, PDE, 0, BS>(P, sq, sacc, Da, irho, lam, mu);
+  __syncthreads();
+  if constexpr (D > 1) {
+    rhs_axis_mfma<D, N, PDE, 1, BS>(P, sq, sacc, Da, irho, lam, mu);
+    __syncthreads();
+  }
+  if constexpr (D > 2) {
+    rhs_axis_mfma<D, N, PDE, 2, BS>(P, sq, sacc, Da, irho, lam, mu);
+    __syncthreads();
+  }
+  time_phase_mfma<D, N, PDE, BS>(sacc, sq, ureg, dt, Ta);
+  __syncthreads();
+}
+
+// Euler volume term, step 1: time-integrated flux of every axis at every
+// spatial node, FB[A][v][k] = sum_l0 w_l0 F_A(q(l0,k)) (one thread per node).
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void euler_time_flux(const PredArgs &P, const double *qf, double *FB) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  const double gm1 = P.g.gamma - 1.0;
+  for (int k = threadIdx.x; k < ND; k += BS) {
+    double fb[D][M];
+#pragma unroll
+    for (int a = 0; a < D; a++)
+#pragma unroll
+      for (int v = 0; v < M; v++) fb[a][v] = 0.0;
+    for (int l0 = 0; l0 < n; l0++) {
+      double q[M], F[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) q[v] = qf[v * NST + l0 * ND + k];
+      const double wl = P.ops.w[l0];
+      euler_flux<D, 0, double>(q, gm1, F);
+#pragma unroll
+      for (int v = 0; v < M; v++) fb[0][v] += wl * F[v];
+      if constexpr (D > 1) {
+        euler_flux<D, 1, double>(q, gm1, F);
+#pragma unroll
+        for (int v = 0; v < M; v++) fb[1][v] += wl * F[v];
+      }
+      if constexpr (D > 2) {
+        euler_flux<D, 2, double>(q, gm1, F);
+#pragma unroll
+        for (int v = 0; v < M; v++) fb[2][v] += wl * F[v];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < D; a++)
+#pragma unroll
+      for (int v = 0; v < M; v++) FB[(a * M + v) * ND + k] = fb[a][v];
+  }
+}
+
+// Euler volume term, step 2 (one thread per DOF), fused with u* = u + dt V:
+//   V(v,k) = sum_A (1/h_A) sum_j Vop[k_A][j] FB[A][v][k with k_A = j]
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void euler_volume_update(const PredArgs &P, const double *FB, const double *ue,
+                                                    double *us, double dt) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND;
+  for (int i = threadIdx.x; i < M * ND; i += BS) {
+    const int v = i / ND, k = i - v * ND;
+    double V = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; a++) {
+      const int st = ipow(n, a);
+      const int ka = (k / st) % n;
+      const double *line = FB + (a * M + v) * ND + (k - ka * st);
+      double s = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; j++) s += P.ops.V[ka * kMaxN + j] * line[j * st];
+      V += s * P.g.inv_h[a];
+    }
+    // dt = 0 (flagged state or t already at t_end) leaves the state untouched
+    us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V;
+  }
+}
+
+// Elastic volume term (one thread per node), fused with u* = u + dt V:
+//   V = -sum_A (1/h_A) B_A Dhat_A qbar,  qbar = sum_l0 w_l0 q(l0)  (B constant in the element)
+template <int D, int N, int BS>
+__device__ __forceinline__ void elastic_volume_update(const PredArgs &P, const double *QB, const double *ue,
+                                                      double *us, double dt, double irho, double lam,
+                                                      double mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = 9, ND = S::ND;
+  for (int k = threadIdx.x; k < ND; k += BS) {
+    double V[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) V[v] = 0.0;
+    auto axis = [&](auto Ac) {
+      constexpr int A = decltype(Ac)::value;
+      constexpr int st = ipow(n, A);
+      const int ka = (k / st) % n;
+      const double *base = QB + (k - ka * st);
+      double g[M], bg[M];
 #pragma unroll
       for (int v = 0; v < M; v++) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < n; j++) s += P.ops.D[k * kMaxN + j] * qv[j][v];
-        gk[v] = s;
+        for (int j = 0; j < n; j++) s += P.ops.D[ka * kMaxN + j] * base[v * ND + j * st];
+        g[v] = s;
       }
-      elastic_bg<A>(gk, irho, lam, mu, bg);
+      elastic_bg<A, double>(g, irho, lam, mu, bg);
 #pragma unroll
-      for (int v = 0; v < M; v++) {
-        const int idx = v * ND + base + k * ST;
-        if (A == 0) sV[idx] = -bg[v] * ih;
-        else sV[idx] -= bg[v] * ih;
-      }
+      for (int v = 0; v < M; v++) V[v] -= bg[v] * P.g.inv_h[A];
+    };
+    axis(std::integral_constant<int, 0>{});
+    axis(std::integral_constant<int, 1>{});
+    axis(std::integral_constant<int, 2>{});
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      const int i = v * ND + k;
+      us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V[v];
     }
   }
 }
 
 // Boundary-extrapolated traces on both faces normal to axis A:
-// trace_s(v, l0, face node) = sum_j phi_j(s) q(v, l0, node with k_A = j).
-template <int D, int N, class PDE, int A>
+// trace_s(v, l0, face node) = sum_j phi_j(s) q(v, l0, node with k_A = j),
+// computed in FP64 and stored as TT.
+template <int D, int N, class PDE, int A, typename TT, int BS>
 __device__ __forceinline__ void traces_axis(const PredArgs &P, const double *sq, int64_t e) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
-  double *t0 = P.trace[A][0] + e * (int64_t)(M * ND);
-  double *t1 = P.trace[A][1] + e * (int64_t)(M * ND);
-  for (int i = threadIdx.x; i < M * ND; i += kBlock) {
+  TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(M * ND);
+  TT *t1 = (TT *)P.trace[A][1] + e * (int64_t)(M * ND);
+  for (int i = threadIdx.x; i < M * ND; i += BS) {
     const int v = i / ND, r = i - v * ND;
     const int l0 = r / NF, kf = r - l0 * NF;
     const int lo = kf % ST, hi = kf / ST;
@@ -269,22 +563,63 @@ __device__ __forceinline__ void traces_axis(const PredArgs &P, const double *sq,
       a0 += P.ops.F0[j] * qj;
       a1 += P.ops.F1[j] * qj;
     }
-    t0[i] = a0;
-    t1[i] = a1;
+    t0[i] = (TT)a0;
+    t1[i] = (TT)a1;
   }
 }
 
-// Space-time predictor (Sec. 2.2) of one element per workgroup, FP64.
-// LDS: sq[M][NST] (space-time DOFs, layout [v][l0][k]) and, when it fits,
-// the accumulator sacc[M][ACC]; otherwise the accumulator lives in HBM.
-template <int D, int N, class PDE, bool kAccLds>
-__global__ void __launch_bounds__(kBlock) k_predictor(const PredArgs P) {
+// Predictor outputs from the final FP64 iterate qf: optional qhat copy, the
+// face traces, the volume terms (scratch of D*M*ND doubles) and
+// u* = u + dt V.
+template <int D, int N, class PDE, typename TT, int BS>
+__device__ __forceinline__ void predictor_outputs(const PredArgs &P, const double *qf, double *scratch,
+                                                  const double *ue, double dt, int64_t e, double irho,
+                                                  double lam, double mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
-  extern __shared__ double smem[];
+  if (P.qhat) {
+    double *qo = P.qhat + e * (int64_t)(M * NST);
+    for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
+  }
+  traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
+  if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
+  if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
+  double *us = P.ustar + e * (int64_t)(M * ND);
+  if constexpr (N == 0) {
+    for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
+  } else if constexpr (!PDE::kElastic) {
+    euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
+    __syncthreads();
+    euler_volume_update<D, N, PDE, BS>(P, scratch, ue, us, dt);
+  } else {
+    for (int i = threadIdx.x; i < M * ND; i += BS) {
+      const int v = i / ND, k = i - v * ND;
+      double a = 0.0;
+#pragma unroll
+      for (int l = 0; l < n; l++) a += P.ops.w[l] * qf[v * NST + l * ND + k];
+      scratch[i] = a;
+    }
+    __syncthreads();
+    elastic_volume_update<D, N, BS>(P, scratch, ue, us, dt, irho, lam, mu);
+  }
+}
+
+// Space-time predictor (Sec. 2.2) of one element per workgroup.
+//  PREC == kFP64: every sweep in FP64; q in LDS region A, the accumulator in
+//    region R (or in HBM when kAccLds is false).
+//  PREC == kFP32/kBF16: sweeps 1..P-1 in FP32 on an FP32 copy of q (region
+//    A), the last sweep in FP64 from that copy; its iterate lands in region
+//    R and feeds the FP64 outputs; traces are stored in FP32.
+//  kMfma: the FP32 sweeps contract on MFMA instead of VALU FMAs.
+//  kBFac: block-size factor (threads = pred_block(D, N, kBFac)).
+template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
+__global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const PredArgs P) {
+  constexpr int BS = pred_block(D, N, kBFac);
+  using S = Shape<D, N>;
+  using L = PredLds<D, N, PDE::M, PREC>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t e = blockIdx.x;
-  double *sq = smem;
-  double *sacc = kAccLds ? smem + M * NST : P.acc_glob + e * (int64_t)(M * S::ACC);
   const double *ue = P.u + e * (int64_t)(M * ND);
   const double dt = *P.dt;
   double irho = 0.0, lam = 0.0, mu = 0.0;
@@ -293,81 +628,65 @@ __global__ void __launch_bounds__(kBlock) k_predictor(const PredArgs P) {
     lam = P.mat[3 * e + 1];
     mu = P.mat[3 * e + 2];
   }
-  // q^0 = u_h(t^n), constant in time (K1^{-1} F0 = 1)
-  for (int i = threadIdx.x; i < M * ND; i += kBlock) {
-    const double val = ue[i];
-    const int v = i / ND, k = i - v * ND;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+  double ureg[NU];  // u of the time lines this thread owns, kept for every sweep
 #pragma unroll
-    for (int l0 = 0; l0 < n; l0++) sq[v * NST + l0 * ND + k] = val;
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    ureg[r] = i < M * ND ? ue[i] : 0.0;
   }
-  __syncthreads();
-  for (int s = 0; s < P.sweeps; s++) {
-    rhs_axis<D, N, PDE, 0>(P, sq, sacc, irho, lam, mu);
-    __syncthreads();
-    if constexpr (D > 1) {
-      rhs_axis<D, N, PDE, 1>(P, sq, sacc, irho, lam, mu);
-      __syncthreads();
-    }
-    if constexpr (D > 2) {
-      rhs_axis<D, N, PDE, 2>(P, sq, sacc, irho, lam, mu);
-      __syncthreads();
-    }
-    // q(l0,k) = u(k) + dt sum_j0 T[l0][j0] R(j0,k)
-    for (int i = threadIdx.x; i < M * ND; i += kBlock) {
+  if constexpr (PREC == kFP64) {
+    double *sq = (double *)smem_raw;
+    double *sacc = kAccLds ? (double *)(smem_raw + L::A) : P.acc_glob + e * (int64_t)(M * S::ACC);
+    // q^0 = u_h(t^n), constant in time (K1^{-1} F0 = 1)
+    for (int i = threadIdx.x; i < M * ND; i += BS) {
+      const double val = ue[i];
       const int v = i / ND, k = i - v * ND;
-      double r[n];
 #pragma unroll
-      for (int j = 0; j < n; j++) r[j] = sacc[v * NST + j * ND + k];
-      const double u0 = ue[i];
-#pragma unroll
-      for (int l = 0; l < n; l++) {
-        double a = 0.0;
-#pragma unroll
-        for (int j = 0; j < n; j++) a += P.ops.T[l * kMaxN + j] * r[j];
-        sq[v * NST + l * ND + k] = u0 + dt * a;
-      }
+      for (int l0 = 0; l0 < n; l0++) sq[v * NST + l0 * ND + k] = val;
     }
     __syncthreads();
-  }
-  if (P.qhat) {
-    double *qo = P.qhat + e * (int64_t)(M * NST);
-    for (int i = threadIdx.x; i < M * NST; i += kBlock) qo[i] = sq[i];
-  }
-  traces_axis<D, N, PDE, 0>(P, sq, e);
-  if constexpr (D > 1) traces_axis<D, N, PDE, 1>(P, sq, e);
-  if constexpr (D > 2) traces_axis<D, N, PDE, 2>(P, sq, e);
-  // volume terms into sV = sacc[0 .. M*ND)
-  double *sV = sacc;
-  if constexpr (N == 0) {
-    for (int i = threadIdx.x; i < M * ND; i += kBlock) sV[i] = 0.0;
-  } else if constexpr (!PDE::kElastic) {
-    volume_axis_euler<D, N, PDE, 0>(P, sq, sV);
-    __syncthreads();
-    if constexpr (D > 1) {
-      volume_axis_euler<D, N, PDE, 1>(P, sq, sV);
-      __syncthreads();
-    }
-    if constexpr (D > 2) volume_axis_euler<D, N, PDE, 2>(P, sq, sV);
+    for (int s = 0; s < P.sweeps; s++)
+      picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, dt, e, irho, lam, mu);
   } else {
-    double *sQ = sacc + M * ND;
-    for (int i = threadIdx.x; i < M * ND; i += kBlock) {
+    constexpr bool kBF = PREC == kBF16;
+    float *sq32 = (float *)smem_raw;
+    double *sR = (double *)(smem_raw + L::A);
+    float *sacc32 = (float *)sR;
+    for (int i = threadIdx.x; i < M * ND; i += BS) {
+      const float val = (float)ue[i];
       const int v = i / ND, k = i - v * ND;
-      double a = 0.0;
 #pragma unroll
-      for (int l = 0; l < n; l++) a += P.ops.w[l] * sq[v * NST + l * ND + k];
-      sQ[i] = a;
+      for (int l0 = 0; l0 < n; l0++) sq32[v * NST + l0 * ND + k] = val;
     }
     __syncthreads();
-    volume_axis_elastic<D, N, 0>(P, sQ, sV, irho, lam, mu);
-    __syncthreads();
-    volume_axis_elastic<D, N, 1>(P, sQ, sV, irho, lam, mu);
-    __syncthreads();
-    volume_axis_elastic<D, N, 2>(P, sQ, sV, irho, lam, mu);
+    const float dtf = (float)dt;
+    if constexpr (PREC == kFP32 && kMfma) {
+      // per-lane A operands: operator rows k = 4c + (lane & 3)
+      float Db[2][n], Tb[2][n];
+      const int lq = threadIdx.x & 3;
+#pragma unroll
+      for (int c = 0; c < 2; c++)
+#pragma unroll
+        for (int j = 0; j < n; j++) {
+          const int k = 4 * c + lq;
+          Db[c][j] = k < n ? P.opsf.D[k * kMaxN + j] : 0.f;
+          Tb[c][j] = k < n ? P.opsf.T[k * kMaxN + j] : 0.f;
+        }
+      for (int s = 0; s + 1 < P.sweeps; s++)
+        picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db,
+                                         Tb);
+    } else {
+      for (int s = 0; s + 1 < P.sweeps; s++)
+        picard_sweep<D, N, PDE, float, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho,
+                                                          (float)lam, (float)mu);
+    }
+    // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
+    // the FP64 accumulator in place
+    picard_sweep<D, N, PDE, double, float, double, false, BS>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
+    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, dt, e, irho, lam, mu);
   }
-  __syncthreads();
-  double *us = P.ustar + e * (int64_t)(M * ND);
-  // dt = 0 (flagged state or t already at t_end) leaves the state untouched
-  for (int i = threadIdx.x; i < M * ND; i += kBlock) us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * sV[i];
 }
 
 // ------------------------------------------------------------ faces
@@ -375,28 +694,34 @@ __global__ void __launch_bounds__(kBlock) k_predictor(const PredArgs P) {
 struct FaceArgs {
   Ops ops;
   Geom g;
-  const double *trace0;  // side-0 traces of axis A (the + neighbour reads these)
-  const double *trace1;  // side-1 traces of axis A
+  const void *trace0;  // side-0 traces of axis A (the + neighbour reads these)
+  const void *trace1;  // side-1 traces of axis A
   const double *mat;
-  double *GL;            // [E][M][NF] face integral for the element on the - side
-  double *GR;            // [E][M][NF] for the element on the + side (non-conservative only)
+  double *GL;          // [E][M][NF] face integral for the element on the - side
+  double *GR;          // [E][M][NF] for the element on the + side (non-conservative only)
 };
 
 // Path-conservative Rusanov jump term (eqs. pc.scheme, rusanov) at every
 // face node and time node of the face between element e (side 1) and its +A
-// neighbour (side 0), integrated in time with the GL weights.  One thread
-// per (face, face node).
-template <int D, int N, class PDE, int A>
+// neighbour (side 0), integrated in time with the GL weights, in FP64 from
+// traces stored as TT.  One thread per (face, face node); the grid is
+// (x-row chunks, ny, nz) so element coordinates need no division.
+template <int D, int N, class PDE, int A, typename TT>
 __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= F.g.E * NF) return;
-  const int64_t e = t / NF;
-  const int kf = (int)(t - e * NF);
-  const int64_t eR = neighbour(e, A, +1, F.g.nel);
-  const double *tm = F.trace1 + e * (int64_t)(M * ND) + kf;
-  const double *tp = F.trace0 + eR * (int64_t)(M * ND) + kf;
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int nx = F.g.nel[0], ny = F.g.nel[1], nz = F.g.nel[2];
+  if (t >= nx * NF) return;
+  const int ix = t / NF, kf = t - ix * NF;
+  const int iy = blockIdx.y, iz = blockIdx.z;
+  const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+  const int jx = (A == 0) ? (ix + 1 == nx ? 0 : ix + 1) : ix;
+  const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
+  const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
+  const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
+  const TT *tm = (const TT *)F.trace1 + e * (int64_t)(M * ND) + kf;
+  const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(M * ND) + kf;
   double GL[M], GR[M];
 #pragma unroll
   for (int v = 0; v < M; v++) GL[v] = GR[v] = 0.0;
@@ -406,13 +731,13 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
       double qm[M], qp[M], Fm[M], Fp[M];
 #pragma unroll
       for (int v = 0; v < M; v++) {
-        qm[v] = tm[(v * n + l0) * NF];
-        qp[v] = tp[(v * n + l0) * NF];
+        qm[v] = (double)tm[(v * n + l0) * NF];
+        qp[v] = (double)tp[(v * n + l0) * NF];
       }
-      euler_flux<D, A>(qm, gamma - 1.0, Fm);
-      euler_flux<D, A>(qp, gamma - 1.0, Fp);
-      const double sm = fabs(qm[1 + A] / qm[0]) + sqrt(gamma * euler_pressure<D>(qm, gamma) / qm[0]);
-      const double sp = fabs(qp[1 + A] / qp[0]) + sqrt(gamma * euler_pressure<D>(qp, gamma) / qp[0]);
+      euler_flux<D, A, double>(qm, gamma - 1.0, Fm);
+      euler_flux<D, A, double>(qp, gamma - 1.0, Fp);
+      const double sm = euler_speed<D, A>(qm, gamma);
+      const double sp = euler_speed<D, A>(qp, gamma);
       const double smax = fmax(sm, sp);
       const double wl = F.ops.w[l0];
 #pragma unroll
@@ -439,8 +764,9 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
     for (int l0 = 0; l0 < n; l0++) {
       double dq[M], bd[M];
 #pragma unroll
-      for (int v = 0; v < M; v++) dq[v] = tp[(v * n + l0) * NF] - tm[(v * n + l0) * NF];
-      elastic_bg<A>(dq, irho, lam, mu, bd);
+      for (int v = 0; v < M; v++)
+        dq[v] = (double)tp[(v * n + l0) * NF] - (double)tm[(v * n + l0) * NF];
+      elastic_bg<A, double>(dq, irho, lam, mu, bd);
       const double wl = F.ops.w[l0];
 #pragma unroll
       for (int v = 0; v < M; v++) {
@@ -470,30 +796,38 @@ struct UpdArgs {
   double *u;
 };
 
-// u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64)
+// u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64).
+// One thread per DOF; grid (x-row chunks, ny, nz).
 template <int D, int N, class PDE>
 __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
-  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (t >= U.g.E * (M * ND)) return;
-  const int64_t e = t / (M * ND);
-  const int r = (int)(t - e * (M * ND));
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  const int nx = U.g.nel[0], ny = U.g.nel[1], nz = U.g.nel[2];
+  if (t >= nx * (M * ND)) return;
+  const int ix = t / (M * ND);
+  const int r = t - ix * (M * ND);
   const int v = r / ND, k = r - v * ND;
+  const int iy = blockIdx.y, iz = blockIdx.z;
+  const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
   double acc = 0.0;
 #pragma unroll
   for (int A = 0; A < D; A++) {
     const int ST = ipow(n, A);
     const int ka = (k / ST) % n;
     const int kf = (k % ST) + (k / (ST * n)) * ST;
-    const int64_t eL = neighbour(e, A, -1, U.g.nel);
+    const int jx = (A == 0) ? (ix == 0 ? nx - 1 : ix - 1) : ix;
+    const int jy = (A == 1) ? (iy == 0 ? ny - 1 : iy - 1) : iy;
+    const int jz = (A == 2) ? (iz == 0 ? nz - 1 : iz - 1) : iz;
+    const int64_t eL = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
     const double gplus = U.GL[A][e * (M * NF) + v * NF + kf];
     const double gminus = PDE::kConservative ? -U.GL[A][eL * (M * NF) + v * NF + kf]
                                              : U.GR[A][eL * (M * NF) + v * NF + kf];
     acc += U.g.inv_h[A] * (U.ops.L1[ka] * gplus + U.ops.L0[ka] * gminus);
   }
+  const int64_t gi = e * (M * ND) + r;
   const double dt = *U.dt;
-  U.u[t] = dt == 0.0 ? U.ustar[t] : U.ustar[t] - dt * acc;
+  U.u[gi] = dt == 0.0 ? U.ustar[gi] : U.ustar[gi] - dt * acc;
 }
 
 // ------------------------------------------------------------ time step
@@ -507,9 +841,11 @@ struct CflArgs {
   int *err;
 };
 
-// One wavefront per element: per-axis maxima of |lambda| over the nodes,
-// S_e = sum_A max_A / h_A, then a block max and one atomicMax on the bit
-// pattern (order independent: positive doubles order like their bits).
+// Per-element wave speed S_e = sum_A (max_k |lambda_A(u_k)|) / h_A and its
+// maximum over the mesh.  Grid (1, ny, nz): each workgroup walks one x-row
+// of elements, one wavefront per element at a time, and issues a single
+// atomicMax on the bit pattern (positive doubles order like their bits, so
+// the result does not depend on the order).
 template <int D, int N, class PDE>
 __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
   using S = Shape<D, N>;
@@ -519,10 +855,12 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
   if (threadIdx.x == 0) bad_any = 0;
   __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int64_t e = (int64_t)blockIdx.x * (kBlock / 64) + wave;
-  double se = 0.0;
+  const int nx = C.g.nel[0], ny = C.g.nel[1];
+  const int64_t row = (int64_t)nx * (blockIdx.y + (int64_t)ny * blockIdx.z);
+  double smax = 0.0;
   int bad = 0;
-  if (e < C.g.E) {
+  for (int ix = wave; ix < nx; ix += kBlock / 64) {
+    const int64_t e = row + ix;
     double lm[3] = {0.0, 0.0, 0.0};
     const double *ue = C.u + e * (int64_t)(M * ND);
     for (int k = lane; k < ND; k += 64) {
@@ -533,12 +871,16 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
         if (!isfinite(q[v])) bad = 1;
       }
       if constexpr (!PDE::kElastic) {
-        const double p = euler_pressure<D>(q, C.g.gamma);
+        const double ir = 1.0 / q[0];
+        double ke = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
+        const double p = (C.g.gamma - 1.0) * (q[D + 1] - 0.5 * ke * ir);
         if (!(q[0] > 0.0) || !(p > 0.0)) bad = 1;
-        const double c = sqrt(C.g.gamma * p / q[0]);
+        const double c = sqrt(C.g.gamma * p * ir);
 #pragma unroll
         for (int A = 0; A < D; A++) {
-          const double l = fabs(q[1 + A] / q[0]) + c;
+          const double l = fabs(q[1 + A] * ir) + c;
           if (!(l >= 0.0)) bad = 1;
           lm[A] = fmax(lm[A], l);
         }
@@ -550,14 +892,16 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
 #pragma unroll
       for (int A = 0; A < D; A++) lm[A] = cp;
     }
+    double se = 0.0;
 #pragma unroll
-    for (int A = 0; A < D; A++)
+    for (int A = 0; A < D; A++) {
       for (int off = 32; off > 0; off >>= 1) lm[A] = fmax(lm[A], __shfl_xor(lm[A], off, 64));
-#pragma unroll
-    for (int A = 0; A < D; A++) se += lm[A] / C.h[A];
+      se += lm[A] / C.h[A];
+    }
+    smax = fmax(smax, se);
   }
   if (bad) atomicOr(&bad_any, 1);
-  if (lane == 0) red[wave] = se;
+  if (lane == 0) red[wave] = smax;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0];

@@ -2,8 +2,11 @@
 // the launch sequence of one step.
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -28,10 +31,14 @@ struct ProbState {
   int sweeps = 0;
   int64_t u_off = 0, u_cnt = 0, q_off = 0, q_cnt = 0;
   KernelSet ks{};
-  bool acc_lds = true;
-  size_t shmem = 0;
+  PredVariant pv{};                 // chosen predictor variant
+  bool tuned = false;               // chosen by timing (else default or forced)
+  double tune_ms = 0.0;             // measured time of the chosen variant on the sample
+  const void *const *face = nullptr;  // face entries for the trace type
+  size_t trace_elt = 8;             // bytes per trace value
+  OpsF opsf{};
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
-  double *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
+  void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   double *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};
 };
 
@@ -92,6 +99,7 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
   if (d.degree > 7) return fail(c, ADER_ERR_UNSUPPORTED, w + "degree > 7 is not built");
   for (int a = 0; a < d.dim; a++) {
     if (d.nelem[a] < 1) return fail(c, ADER_ERR_INVALID, w + "nelem must be >= 1");
+    if (d.nelem[a] > 65535) return fail(c, ADER_ERR_UNSUPPORTED, w + "nelem must be <= 65535");
     if (!(d.hi[a] > d.lo[a]) || !isfinite(d.hi[a] - d.lo[a]))
       return fail(c, ADER_ERR_INVALID, w + "hi must exceed lo");
   }
@@ -110,7 +118,6 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
   }
   if (d.prec != ADER_FP64 && d.prec != ADER_FP32 && d.prec != ADER_BF16)
     return fail(c, ADER_ERR_INVALID, w + "unknown precision");
-  if (d.prec != ADER_FP64) return fail(c, ADER_ERR_UNSUPPORTED, w + "only FP64 predictor is built");
   if (d.picard_iters < 0) return fail(c, ADER_ERR_INVALID, w + "picard_iters must be >= 0");
   if (!(d.cfl > 0.0) || d.cfl > 1.0) return fail(c, ADER_ERR_INVALID, w + "cfl must be in (0, 1]");
   return ADER_OK;
@@ -185,11 +192,113 @@ __global__ void k_totals_final(const double *partial, int nblk, int m, double *o
 
 int64_t blocks_for(int64_t work) { return (work + kBlock - 1) / kBlock; }
 
-ader_status launch(ader_ctx *c, const void *fn, int64_t grid, size_t shmem, void *arg) {
+ader_status launch(ader_ctx *c, const void *fn, int64_t grid, size_t shmem, void *arg,
+                   int threads = kBlock, int gy = 1, int gz = 1) {
   if (grid <= 0) return ADER_OK;
-  if (grid > 0x7fffffff) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
+  if (grid > 0x7fffffff || gy > 65535 || gz > 65535) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
   void *args[] = {arg};
-  HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(kBlock), args, shmem, c->stream));
+  HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid, gy, gz), dim3(threads), args, shmem, c->stream));
+  return ADER_OK;
+}
+
+// Uniform state u[e][v][k] = val[v] (used to time predictor variants).
+__global__ void k_fill_state(double *u, int64_t count, int m, int nd, double v0, double v1, double v2,
+                             double v3, double v4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const int v = (int)((i / nd) % m);
+  const double vals[5] = {v0, v1, v2, v3, v4};
+  u[i] = v < 5 ? vals[v] : 0.0;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::string> g_tune_cache;  // configuration -> variant name
+
+PredArgs pred_args(ProbState &s, const double *u, const double *dt, double *qhat) {
+  PredArgs a{};
+  a.ops = s.ops;
+  a.opsf = s.opsf;
+  a.g = s.g;
+  a.u = u;
+  a.dt = dt;
+  a.mat = s.mat;
+  a.ustar = s.ustar;
+  for (int ax = 0; ax < 3; ax++)
+    for (int sd = 0; sd < 2; sd++) a.trace[ax][sd] = s.trace[ax][sd];
+  a.qhat = qhat;
+  a.acc_glob = s.acc;
+  a.sweeps = s.sweeps;
+  return a;
+}
+
+// Time every candidate predictor variant on a uniform state of up to 32768
+// elements (the kernels have no data-dependent branches) and keep the
+// fastest.  Results are cached per configuration for the process.
+ader_status tune_predictor(ader_ctx *c, ProbState &s, int p, const std::vector<PredVariant> &cand) {
+  const int64_t Et = s.E < 32768 ? s.E : 32768;
+  const std::string key = std::to_string(s.D) + "/" + std::to_string(s.N) + "/" +
+                          std::to_string(s.desc.pde) + "/" + std::to_string(s.desc.prec) + "/" +
+                          std::to_string(Et) + "/" + std::to_string(s.sweeps);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end())
+      for (const PredVariant &v : cand)
+        if (it->second == v.name) {
+          s.pv = v;
+          s.tuned = true;
+          return ADER_OK;
+        }
+  }
+  double *ut = nullptr;
+  const int64_t cnt = Et * s.m * s.nd;
+  if (hipMalloc(&ut, cnt * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    return ADER_OK;  // no room to tune: keep the default
+  }
+  const double ie = 1.0 / (s.desc.gamma - 1.0);  // Euler: rho = 1, v = 0, p = 1
+  const unsigned nb = (unsigned)((cnt + 255) / 256);
+  if (s.desc.pde == ADER_EULER)
+    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->stream, ut, cnt, s.m, s.nd, 1.0, 0.0, 0.0,
+                       s.D == 2 ? ie : 0.0, s.D == 3 ? ie : 0.0);
+  else
+    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->stream, ut, cnt, s.m, s.nd, 0.0, 0.0, 0.0,
+                       1.0, 1.0);
+  const double dt_tune = 1e-6;
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dt + p, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  hipEvent_t e0, e1;
+  HIP_OR_FAIL(c, hipEventCreate(&e0));
+  HIP_OR_FAIL(c, hipEventCreate(&e1));
+  PredArgs a = pred_args(s, ut, c->dt + p, nullptr);
+  double best = 1e30;
+  PredVariant bestv = s.pv;
+  ader_status st = ADER_OK;
+  for (const PredVariant &v : cand) {
+    if ((st = launch(c, v.fn, Et, v.lds, &a, v.threads))) break;  // warm-up
+    HIP_OR_FAIL(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < 3 && !st; r++) st = launch(c, v.fn, Et, v.lds, &a, v.threads);
+    HIP_OR_FAIL(c, hipEventRecord(e1, c->stream));
+    HIP_OR_FAIL(c, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_OR_FAIL(c, hipEventElapsedTime(&ms, e0, e1));
+    if (st) break;
+    if (ms / 3.0 < best) {
+      best = ms / 3.0;
+      bestv = v;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  (void)hipFree(ut);
+  if (st) return st;
+  const double zero = 0.0;
+  HIP_OR_FAIL(c, hipMemcpy(c->dt + p, &zero, sizeof(double), hipMemcpyHostToDevice));
+  s.pv = bestv;
+  s.tuned = true;
+  s.tune_ms = best;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = bestv.name;
   return ADER_OK;
 }
 
@@ -203,7 +312,7 @@ ader_status run_cfl(ader_ctx *c, const double *u, const double *t_end_host) {
     a.mat = s.mat;
     a.smax_bits = c->smax + p;
     a.err = c->err;
-    ader_status st = launch(c, s.ks.cfl, (s.E + kBlock / 64 - 1) / (kBlock / 64), 0, &a);
+    ader_status st = launch(c, s.ks.cfl, 1, 0, &a, kBlock, s.g.nel[1], s.g.nel[2]);
     if (st) return st;
     const double te = t_end_host ? t_end_host[p] : INFINITY;
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, c->stream, c->smax + p, c->err, s.coef, te,
@@ -216,19 +325,8 @@ ader_status run_cfl(ader_ctx *c, const double *u, const double *t_end_host) {
 ader_status run_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat) {
   for (size_t p = 0; p < c->P.size(); p++) {
     ProbState &s = c->P[p];
-    PredArgs a{};
-    a.ops = s.ops;
-    a.g = s.g;
-    a.u = u + s.u_off;
-    a.dt = (dt_dev ? dt_dev : c->dt) + p;
-    a.mat = s.mat;
-    a.ustar = s.ustar;
-    for (int ax = 0; ax < 3; ax++)
-      for (int sd = 0; sd < 2; sd++) a.trace[ax][sd] = s.trace[ax][sd];
-    a.qhat = qhat ? qhat + s.q_off : nullptr;
-    a.acc_glob = s.acc;
-    a.sweeps = s.sweeps;
-    ader_status st = launch(c, s.acc_lds ? s.ks.pred_lds : s.ks.pred_glob, s.E, s.shmem, &a);
+    PredArgs a = pred_args(s, u + s.u_off, (dt_dev ? dt_dev : c->dt) + p, qhat ? qhat + s.q_off : nullptr);
+    ader_status st = launch(c, s.pv.fn, s.E, s.pv.lds, &a, s.pv.threads);
     if (st) return st;
   }
   return ADER_OK;
@@ -246,7 +344,8 @@ ader_status run_faces(ader_ctx *c) {
       f.mat = s.mat;
       f.GL = s.GL[ax];
       f.GR = s.GR[ax];
-      ader_status st = launch(c, s.ks.face[ax], blocks_for(s.E * s.nf), 0, &f);
+      ader_status st = launch(c, s.face[ax], blocks_for((int64_t)s.g.nel[0] * s.nf), 0, &f, kBlock,
+                              s.g.nel[1], s.g.nel[2]);
       if (st) return st;
     }
   }
@@ -266,7 +365,8 @@ ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
       a.GR[ax] = s.GR[ax];
     }
     a.u = u + s.u_off;
-    ader_status st = launch(c, s.ks.update, blocks_for(s.E * s.m * s.nd), 0, &a);
+    ader_status st = launch(c, s.ks.update, blocks_for((int64_t)s.g.nel[0] * s.m * s.nd), 0, &a, kBlock,
+                            s.g.nel[1], s.g.nel[2]);
     if (st) return st;
   }
   return ADER_OK;
@@ -357,6 +457,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     return bail(ADER_ERR_DEVICE);
   }
   c->P.resize(nprob);
+  std::vector<std::vector<PredVariant>> tune_list;  // per problem: candidates to time
   int64_t uoff = 0, qoff = 0, moff = 0;
   for (int i = 0; i < nprob; i++) {
     const ader_problem &d = probs[i];
@@ -396,36 +497,62 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     uoff += s.u_cnt;
     qoff += s.q_cnt;
     moff += s.m;
-    const size_t q_bytes = (size_t)s.m * s.nst * sizeof(double);
+    for (int k = 0; k < kMaxN * kMaxN; k++) {
+      s.opsf.D[k] = (float)s.ops.D[k];
+      s.opsf.T[k] = (float)s.ops.T[k];
+    }
     const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
-    if (q_bytes + acc_bytes <= kLdsBytes) {
-      s.acc_lds = true;
-      s.shmem = q_bytes + acc_bytes;
-    } else if (q_bytes <= kLdsBytes) {
-      s.acc_lds = false;
-      s.shmem = q_bytes;
-    } else {
+    s.trace_elt = d.prec == ADER_FP64 ? sizeof(double) : sizeof(float);
+    s.face = d.prec == ADER_FP64 ? s.ks.face64 : s.ks.face32;
+    // candidate predictor variants: this precision, within the LDS budget;
+    // for FP64 the HBM-accumulator variant only when no LDS variant fits
+    std::vector<PredVariant> cand;
+    const int want = d.prec == ADER_FP64 ? kFP64 : (d.prec == ADER_FP32 ? kFP32 : kBF16);
+    for (int pass = 0; pass < 2 && cand.empty(); pass++)
+      for (int v = 0; v < s.ks.npred; v++) {
+        const PredVariant &pv = s.ks.pred[v];
+        if (pv.prec != want || pv.lds > kLdsBytes || pv.acc_lds != (pass == 0)) continue;
+        hipFuncAttributes fa;
+        if (hipFuncGetAttributes(&fa, pv.fn) != hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        if (fa.localSizeBytes > 0) continue;  // register spills to scratch: never competitive
+        if (hipFuncSetAttribute(pv.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pv.lds) !=
+            hipSuccess) {
+          (void)hipGetLastError();
+          continue;
+        }
+        cand.push_back(pv);
+      }
+    if (cand.empty()) {
       c->msg = "problem " + std::to_string(i) + ": space-time DOFs of one element exceed LDS";
       return bail(ADER_ERR_UNSUPPORTED);
     }
-    const void *fn = s.acc_lds ? s.ks.pred_lds : s.ks.pred_glob;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)s.shmem) !=
-        hipSuccess) {
-      (void)hipGetLastError();
-      c->msg = "cannot reserve " + std::to_string(s.shmem) + " bytes of LDS";
-      return bail(ADER_ERR_UNSUPPORTED);
-    }
+    s.pv = cand[0];
+    const char *force = getenv("ADER_VARIANT");
+    bool forced = false;
+    if (force && *force)
+      for (const PredVariant &pv : cand)
+        if (strcmp(pv.name, force) == 0) {
+          s.pv = pv;
+          forced = true;
+        }
+    const char *tune_env = getenv("ADER_AUTOTUNE");
+    const bool tune = !forced && cand.size() > 1 && !(tune_env && strcmp(tune_env, "0") == 0);
+    tune_list.push_back(tune ? cand : std::vector<PredVariant>());
     // device buffers
     const size_t ub = (size_t)s.u_cnt * sizeof(double);
     const size_t gb = (size_t)s.E * s.m * s.nf * sizeof(double);
     if ((st = dalloc(c, (void **)&s.ustar, ub))) return bail(st);
+    const size_t tb = (size_t)s.u_cnt * s.trace_elt;
     for (int a = 0; a < s.D; a++) {
       for (int sd = 0; sd < 2; sd++)
-        if ((st = dalloc(c, (void **)&s.trace[a][sd], ub))) return bail(st);
+        if ((st = dalloc(c, (void **)&s.trace[a][sd], tb))) return bail(st);
       if ((st = dalloc(c, (void **)&s.GL[a], gb))) return bail(st);
       if (d.pde == ADER_ELASTIC && (st = dalloc(c, (void **)&s.GR[a], gb))) return bail(st);
     }
-    if (!s.acc_lds && (st = dalloc(c, (void **)&s.acc, (size_t)s.E * acc_bytes))) return bail(st);
+    if (!s.pv.acc_lds && (st = dalloc(c, (void **)&s.acc, (size_t)s.E * acc_bytes))) return bail(st);
     if (d.pde == ADER_ELASTIC) {
       if ((st = dalloc(c, (void **)&s.mat, (size_t)s.E * 3 * sizeof(double)))) return bail(st);
       if (hipMemcpy(s.mat, d.material, (size_t)s.E * 3 * sizeof(double), hipMemcpyHostToDevice) !=
@@ -453,6 +580,8 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     c->msg = "initialisation failed";
     return bail(ADER_ERR_DEVICE);
   }
+  for (int i = 0; i < nprob; i++)
+    if (!tune_list[i].empty() && (st = tune_predictor(c, c->P[i], i, tune_list[i]))) return bail(st);
   *out = c;
   return ADER_OK;
 }
@@ -589,6 +718,16 @@ ader_status ader_totals(ader_ctx *c, const double *u, double *sums_host) {
   HIP_OR_FAIL(c, hipMemcpyAsync(sums_host, c->sums, (size_t)c->total_m * sizeof(double),
                                 hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+ader_status ader_describe(const ader_ctx *c, int32_t prob, char *buf, int32_t len) {
+  if (!c || !buf || len <= 0 || prob < 0 || prob >= (int32_t)c->P.size()) return ADER_ERR_INVALID;
+  const ProbState &s = c->P[prob];
+  snprintf(buf, (size_t)len,
+           "predictor=%s threads=%d lds_bytes=%zu sweeps=%d selection=%s tuned_ms=%.4f trace_bytes=%zu",
+           s.pv.name, s.pv.threads, s.pv.lds, s.sweeps, s.tuned ? "autotuned" : "default", s.tune_ms,
+           s.trace_elt);
   return ADER_OK;
 }
 

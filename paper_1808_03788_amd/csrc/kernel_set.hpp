@@ -4,24 +4,66 @@
 
 namespace ader {
 
+// One predictor entry point and its launch shape.
+struct PredVariant {
+  const void *fn = nullptr;
+  int threads = 0;
+  size_t lds = 0;
+  int prec = 0;       // Prec
+  bool acc_lds = true;
+  bool mfma = false;
+  const char *name = "";
+};
+
+constexpr int kMaxVariants = 12;
+
 struct KernelSet {
-  const void *pred_lds = nullptr;   // predictor, accumulator in LDS
-  const void *pred_glob = nullptr;  // predictor, accumulator in HBM
-  const void *face[3] = {nullptr, nullptr, nullptr};
+  PredVariant pred[kMaxVariants];
+  int npred = 0;
+  const void *face64[3] = {nullptr, nullptr, nullptr};  // FP64 traces
+  const void *face32[3] = {nullptr, nullptr, nullptr};  // FP32 traces
   const void *update = nullptr;
   const void *cfl = nullptr;
   int M = 0, n = 0, ND = 0, NST = 0, NF = 0, ACC = 0;
 };
 
+template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
+void add_variant(KernelSet &k, const char *name) {
+  using L = PredLds<D, N, PDE::M, PREC>;
+  PredVariant v;
+  v.fn = (const void *)&k_predictor<D, N, PDE, PREC, kAccLds, kMfma, kBFac>;
+  v.threads = pred_block(D, N, kBFac);
+  v.lds = (PREC == kFP64 && !kAccLds) ? L::A : L::A + L::R;
+  v.prec = PREC;
+  v.acc_lds = kAccLds;
+  v.mfma = kMfma;
+  v.name = name;
+  k.pred[k.npred++] = v;
+}
+
 template <int D, int N, class PDE>
 KernelSet make_kernel_set() {
   using S = Shape<D, N>;
   KernelSet k;
-  k.pred_lds = (const void *)&k_predictor<D, N, PDE, true>;
-  k.pred_glob = (const void *)&k_predictor<D, N, PDE, false>;
-  k.face[0] = (const void *)&k_face<D, N, PDE, 0>;
-  if constexpr (D > 1) k.face[1] = (const void *)&k_face<D, N, PDE, 1>;
-  if constexpr (D > 2) k.face[2] = (const void *)&k_face<D, N, PDE, 2>;
+  add_variant<D, N, PDE, kFP64, true, false, 1>(k, "fp64-valu-b1");
+  add_variant<D, N, PDE, kFP64, true, false, 2>(k, "fp64-valu-b2");
+  add_variant<D, N, PDE, kFP64, false, false, 1>(k, "fp64-valu-hbmacc-b1");
+  add_variant<D, N, PDE, kFP32, true, false, 1>(k, "fp32-valu-b1");
+  add_variant<D, N, PDE, kFP32, true, false, 2>(k, "fp32-valu-b2");
+  add_variant<D, N, PDE, kFP32, true, true, 1>(k, "fp32-mfma-b1");
+  add_variant<D, N, PDE, kFP32, true, true, 2>(k, "fp32-mfma-b2");
+  add_variant<D, N, PDE, kBF16, true, false, 1>(k, "bf16-valu-b1");
+  add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
+  k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double>;
+  k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float>;
+  if constexpr (D > 1) {
+    k.face64[1] = (const void *)&k_face<D, N, PDE, 1, double>;
+    k.face32[1] = (const void *)&k_face<D, N, PDE, 1, float>;
+  }
+  if constexpr (D > 2) {
+    k.face64[2] = (const void *)&k_face<D, N, PDE, 2, double>;
+    k.face32[2] = (const void *)&k_face<D, N, PDE, 2, float>;
+  }
   k.update = (const void *)&k_update<D, N, PDE>;
   k.cfl = (const void *)&k_cfl<D, N, PDE>;
   k.M = PDE::M;

@@ -279,3 +279,66 @@ def test_multiple_problems_one_context(A, orc):
         uo, _ = orc_run(orc, p, u0, 3, te)
         check(p, ug, uo, what=f"multi {p.pde} d={p.dim}")
     ctx.close()
+
+
+# ---------------------------------------------------------------- mixed precision
+
+TOL32 = 1e-6
+
+MIXED_CASES = [
+    ("euler3d_N4", lambda prec: I.Problem(dim=3, N=4, nel=(5, 6, 7), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec),
+     lambda p: I.density_wave(p), 20),
+    ("vortex2d_N3", lambda prec: I.vortex_problem(nel=16, N=3, prec=prec), I.isentropic_vortex, 20),
+    ("elastic_N3", lambda prec: I.elastic_problem(nel=4, N=3, prec=prec),
+     lambda p: I.stress_pulse(p, width=0.2), 20),
+    ("elastic_N5", lambda prec: I.elastic_problem(nel=3, N=5, prec=prec),
+     lambda p: I.stress_pulse(p, width=0.25), 5),
+    ("euler3d_N6", lambda prec: I.Problem(dim=3, N=6, nel=(2, 3, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec),
+     lambda p: I.density_wave(p), 4),
+]
+
+
+@pytest.mark.parametrize("name,mk,init,steps", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_fp32_predictor_within_1e6(A, orc, name, mk, init, steps):
+    prob = mk("fp32")
+    u0 = init(prob)
+    say(f"[fp32] {name} E={prob.E} N={prob.N} steps={steps}")
+    ug, _ = gpu_run(A, prob, u0, steps)
+    uo, _ = orc_run(orc, prob, u0, steps)
+    check(prob, ug, uo, tol=TOL32, what=f"fp32 {name}")
+
+
+@pytest.mark.parametrize("name,mk,init,steps", MIXED_CASES[:3], ids=[c[0] for c in MIXED_CASES[:3]])
+def test_bf16_predictor_error_stated(A, orc, name, mk, init, steps):
+    """BF16 contraction inputs: the error is stated, bounded loosely, and the
+    FP64 residual sweep keeps it well below the BF16 unit round-off."""
+    prob = mk("bf16")
+    u0 = init(prob)
+    ug, _ = gpu_run(A, prob, u0, steps)
+    uo, _ = orc_run(orc, prob, u0, steps)
+    err = I.rel_l2(prob, ug, uo)
+    say(f"[bf16] {name}: rel L2 vs oracle {err:.3e}")
+    assert err < 4e-3
+
+
+def test_fp32_design_order_vortex(A):
+    """The FP32-sweep path keeps the order of the scheme (vortex, N=3, t=1)."""
+    import math
+    errs = []
+    for nel in (8, 16, 32):
+        prob = I.vortex_problem(nel=nel, N=3, prec="fp32")
+        u0 = I.isentropic_vortex(prob)
+        import torch
+        ctx = A.Context([prob])
+        u = ctx.upload([u0])
+        steps = 0
+        while ctx.time()[0] < 1.0 and steps < 2000:
+            ctx.step(u, 1.0)
+            steps += 1
+        torch.cuda.synchronize()
+        ug = ctx.download(u)[0]
+        ctx.close()
+        errs.append(I.l2_per_var(prob, ug - I.isentropic_vortex(prob, 1.0))[0])
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    say(f"[fp32] vortex errors {errs} orders {orders}")
+    assert orders[-1] > 3.6
