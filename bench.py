@@ -53,7 +53,7 @@ def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
     nf = nd // n
     u = 8 * m * nd
     trace = trace_bytes * m * nd            # one face trace block of one element
-    g = 8 * m * nf                           # one face integral block
+    g = trace_bytes * m * nf                 # one face integral block (stored like the traces)
     return {
         "cfl": u,
         "predictor": u + u + 2 * d * trace,  # read u, write u*, write 2d traces

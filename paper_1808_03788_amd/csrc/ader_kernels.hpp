@@ -697,89 +697,100 @@ struct FaceArgs {
   const void *trace0;  // side-0 traces of axis A (the + neighbour reads these)
   const void *trace1;  // side-1 traces of axis A
   const double *mat;
-  double *GL;          // [E][M][NF] face integral for the element on the - side
-  double *GR;          // [E][M][NF] for the element on the + side (non-conservative only)
+  void *GL;            // [E][M][NF] face integral for the element on the - side (GT)
+  void *GR;            // [E][M][NF] for the element on the + side (non-conservative only)
 };
+
+// Faces handled by one workgroup of the face kernel: as many whole faces as
+// fit n*NF (time node, face node) pairs into 256 threads, at least one.
+__host__ __device__ constexpr int face_per_block(int D, int N) {
+  return kBlock / (ipow(N + 1, D)) > 0 ? kBlock / (ipow(N + 1, D)) : 1;
+}
 
 // Path-conservative Rusanov jump term (eqs. pc.scheme, rusanov) at every
 // face node and time node of the face between element e (side 1) and its +A
 // neighbour (side 0), integrated in time with the GL weights, in FP64 from
-// traces stored as TT.  One thread per (face, face node); the grid is
-// (x-row chunks, ny, nz) so element coordinates need no division.
-template <int D, int N, class PDE, int A, typename TT>
+// traces stored as TT, stored as GT.  One thread per (face, time node, face node), so that
+// consecutive threads read consecutive trace values; the time integral is
+// summed through LDS in time-node order.  Grid: (x-row chunks of FPB faces,
+// ny, nz), so element coordinates need no division.
+template <int D, int N, class PDE, int A, typename TT, typename GT>
 __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
+  constexpr int FPB = face_per_block(D, N);
+  constexpr int NI = FPB * n * NF;            // (face, l0, kf) items of the block
+  constexpr int NG = PDE::kConservative ? 1 : 2;
+  __shared__ double sD[NG][FPB][M][n * NF];  // w_l0 * D^-(l0, kf) per face
   const int nx = F.g.nel[0], ny = F.g.nel[1], nz = F.g.nel[2];
-  if (t >= nx * NF) return;
-  const int ix = t / NF, kf = t - ix * NF;
   const int iy = blockIdx.y, iz = blockIdx.z;
-  const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
-  const int jx = (A == 0) ? (ix + 1 == nx ? 0 : ix + 1) : ix;
-  const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
-  const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
-  const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
-  const TT *tm = (const TT *)F.trace1 + e * (int64_t)(M * ND) + kf;
-  const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(M * ND) + kf;
-  double GL[M], GR[M];
-#pragma unroll
-  for (int v = 0; v < M; v++) GL[v] = GR[v] = 0.0;
-  if constexpr (!PDE::kElastic) {
-    const double gamma = F.g.gamma;
-    for (int l0 = 0; l0 < n; l0++) {
-      double qm[M], qp[M], Fm[M], Fp[M];
-#pragma unroll
-      for (int v = 0; v < M; v++) {
-        qm[v] = (double)tm[(v * n + l0) * NF];
-        qp[v] = (double)tp[(v * n + l0) * NF];
-      }
-      euler_flux<D, A, double>(qm, gamma - 1.0, Fm);
-      euler_flux<D, A, double>(qp, gamma - 1.0, Fp);
-      const double sm = euler_speed<D, A>(qm, gamma);
-      const double sp = euler_speed<D, A>(qp, gamma);
-      const double smax = fmax(sm, sp);
-      const double wl = F.ops.w[l0];
-#pragma unroll
-      for (int v = 0; v < M; v++)
-        GL[v] += wl * (0.5 * (Fp[v] + Fm[v]) - 0.5 * smax * (qp[v] - qm[v]));
-    }
-    double *gl = F.GL + e * (int64_t)(M * NF) + kf;
-#pragma unroll
-    for (int v = 0; v < M; v++) gl[v * NF] = GL[v];
-  } else {
-    // material path integral with the 3-point Gauss-Legendre rule on [0,1]
-    const double rL = F.mat[3 * e], lL = F.mat[3 * e + 1], mL = F.mat[3 * e + 2];
-    const double rR = F.mat[3 * eR], lR = F.mat[3 * eR + 1], mR = F.mat[3 * eR + 2];
-    const double gs[3] = {0.5 - 0.1 * sqrt(15.0), 0.5, 0.5 + 0.1 * sqrt(15.0)};
-    const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
-    double irho = 0.0, lam = 0.0, mu = 0.0;
-#pragma unroll
-    for (int g = 0; g < 3; g++) {
-      irho += gw[g] / (rL + gs[g] * (rR - rL));
-      lam += gw[g] * (lL + gs[g] * (lR - lL));
-      mu += gw[g] * (mL + gs[g] * (mR - mL));
-    }
-    const double smax = fmax(sqrt((lL + 2.0 * mL) / rL), sqrt((lR + 2.0 * mR) / rR));
-    for (int l0 = 0; l0 < n; l0++) {
-      double dq[M], bd[M];
-#pragma unroll
-      for (int v = 0; v < M; v++)
-        dq[v] = (double)tp[(v * n + l0) * NF] - (double)tm[(v * n + l0) * NF];
-      elastic_bg<A, double>(dq, irho, lam, mu, bd);
-      const double wl = F.ops.w[l0];
-#pragma unroll
-      for (int v = 0; v < M; v++) {
-        GL[v] += wl * (0.5 * (bd[v] - smax * dq[v]));
-        GR[v] += wl * (0.5 * (bd[v] + smax * dq[v]));
-      }
-    }
-    double *gl = F.GL + e * (int64_t)(M * NF) + kf;
-    double *gr = F.GR + e * (int64_t)(M * NF) + kf;
+  for (int it = threadIdx.x; it < NI; it += kBlock) {
+    const int f = it / (n * NF), r = it - f * (n * NF);  // r = l0 * NF + kf
+    const int l0 = r / NF, kf = r - l0 * NF;
+    const int ix = blockIdx.x * FPB + f;
+    if (ix >= nx) continue;
+    const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+    const int jx = (A == 0) ? (ix + 1 == nx ? 0 : ix + 1) : ix;
+    const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
+    const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
+    const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
+    const TT *tm = (const TT *)F.trace1 + e * (int64_t)(M * ND) + r;
+    const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(M * ND) + r;
+    double qm[M], qp[M];
 #pragma unroll
     for (int v = 0; v < M; v++) {
-      gl[v * NF] = GL[v];
-      gr[v * NF] = GR[v];
+      qm[v] = (double)tm[v * n * NF];
+      qp[v] = (double)tp[v * n * NF];
+    }
+    const double wl = F.ops.w[l0];
+    if constexpr (!PDE::kElastic) {
+      const double gamma = F.g.gamma;
+      double Fm[M], Fp[M];
+      euler_flux<D, A, double>(qm, gamma - 1.0, Fm);
+      euler_flux<D, A, double>(qp, gamma - 1.0, Fp);
+      const double smax = fmax(euler_speed<D, A>(qm, gamma), euler_speed<D, A>(qp, gamma));
+#pragma unroll
+      for (int v = 0; v < M; v++)
+        sD[0][f][v][r] = wl * (0.5 * (Fp[v] + Fm[v]) - 0.5 * smax * (qp[v] - qm[v]));
+    } else {
+      // material path integral with the 3-point Gauss-Legendre rule on [0,1]
+      const double rL = F.mat[3 * e], lL = F.mat[3 * e + 1], mL = F.mat[3 * e + 2];
+      const double rR = F.mat[3 * eR], lR = F.mat[3 * eR + 1], mR = F.mat[3 * eR + 2];
+      const double gs[3] = {0.5 - 0.1 * sqrt(15.0), 0.5, 0.5 + 0.1 * sqrt(15.0)};
+      const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+      double irho = 0.0, lam = 0.0, mu = 0.0;
+#pragma unroll
+      for (int g = 0; g < 3; g++) {
+        irho += gw[g] / (rL + gs[g] * (rR - rL));
+        lam += gw[g] * (lL + gs[g] * (lR - lL));
+        mu += gw[g] * (mL + gs[g] * (mR - mL));
+      }
+      const double smax = fmax(sqrt((lL + 2.0 * mL) / rL), sqrt((lR + 2.0 * mR) / rR));
+      double dq[M], bd[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) dq[v] = qp[v] - qm[v];
+      elastic_bg<A, double>(dq, irho, lam, mu, bd);
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        sD[0][f][v][r] = wl * (0.5 * (bd[v] - smax * dq[v]));
+        sD[NG - 1][f][v][r] = wl * (0.5 * (bd[v] + smax * dq[v]));
+      }
+    }
+  }
+  __syncthreads();
+  // G(v, kf) = sum over time nodes, in time-node order
+  for (int it = threadIdx.x; it < FPB * M * NF; it += kBlock) {
+    const int f = it / (M * NF), r = it - f * (M * NF);
+    const int v = r / NF, kf = r - v * NF;
+    const int ix = blockIdx.x * FPB + f;
+    if (ix >= nx) continue;
+    const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+#pragma unroll
+    for (int g = 0; g < NG; g++) {
+      double acc = 0.0;
+#pragma unroll
+      for (int l0 = 0; l0 < n; l0++) acc += sD[g][f][v][l0 * NF + kf];
+      ((GT *)(g == 0 ? F.GL : F.GR))[e * (int64_t)(M * NF) + r] = (GT)acc;
     }
   }
 }
@@ -791,26 +802,26 @@ struct UpdArgs {
   Geom g;
   const double *ustar;
   const double *dt;
-  const double *GL[3];
-  const double *GR[3];
+  const void *GL[3];   // GT
+  const void *GR[3];
   double *u;
 };
 
-// u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64).
-// One thread per DOF; grid (x-row chunks, ny, nz).
-template <int D, int N, class PDE>
+// u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64
+// arithmetic; face integrals stored as GT).  One thread per node, all M
+// variables; grid (x-row chunks, ny, nz).
+template <int D, int N, class PDE, typename GT>
 __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
   const int t = blockIdx.x * kBlock + threadIdx.x;
   const int nx = U.g.nel[0], ny = U.g.nel[1], nz = U.g.nel[2];
-  if (t >= nx * (M * ND)) return;
-  const int ix = t / (M * ND);
-  const int r = t - ix * (M * ND);
-  const int v = r / ND, k = r - v * ND;
+  if (t >= nx * ND) return;
+  const int ix = t / ND, k = t - ix * ND;
   const int iy = blockIdx.y, iz = blockIdx.z;
   const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
-  double acc = 0.0;
+  const GT *gp[D], *gm[D];
+  double cp[D], cm[D];
 #pragma unroll
   for (int A = 0; A < D; A++) {
     const int ST = ipow(n, A);
@@ -820,14 +831,22 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
     const int jy = (A == 1) ? (iy == 0 ? ny - 1 : iy - 1) : iy;
     const int jz = (A == 2) ? (iz == 0 ? nz - 1 : iz - 1) : iz;
     const int64_t eL = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
-    const double gplus = U.GL[A][e * (M * NF) + v * NF + kf];
-    const double gminus = PDE::kConservative ? -U.GL[A][eL * (M * NF) + v * NF + kf]
-                                             : U.GR[A][eL * (M * NF) + v * NF + kf];
-    acc += U.g.inv_h[A] * (U.ops.L1[ka] * gplus + U.ops.L0[ka] * gminus);
+    gp[A] = (const GT *)U.GL[A] + e * (M * NF) + kf;
+    gm[A] = (const GT *)(PDE::kConservative ? U.GL[A] : U.GR[A]) + eL * (M * NF) + kf;
+    cp[A] = U.g.inv_h[A] * U.ops.L1[ka];
+    // the - face: conservative systems use -G of the face owned by eL
+    cm[A] = PDE::kConservative ? -U.g.inv_h[A] * U.ops.L0[ka] : U.g.inv_h[A] * U.ops.L0[ka];
   }
-  const int64_t gi = e * (M * ND) + r;
   const double dt = *U.dt;
-  U.u[gi] = dt == 0.0 ? U.ustar[gi] : U.ustar[gi] - dt * acc;
+  const int64_t base = e * (M * ND) + k;
+#pragma unroll
+  for (int v = 0; v < M; v++) {
+    double acc = 0.0;
+#pragma unroll
+    for (int A = 0; A < D; A++) acc += cp[A] * (double)gp[A][v * NF] + cm[A] * (double)gm[A][v * NF];
+    const double us = U.ustar[base + v * ND];
+    U.u[base + v * ND] = dt == 0.0 ? us : us - dt * acc;
+  }
 }
 
 // ------------------------------------------------------------ time step

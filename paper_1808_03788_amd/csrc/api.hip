@@ -39,7 +39,8 @@ struct ProbState {
   OpsF opsf{};
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
   void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
-  double *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};
+  void *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};  // trace type
+  const void *update = nullptr;     // update entry for the face-integral type
 };
 
 }  // namespace
@@ -344,8 +345,9 @@ ader_status run_faces(ader_ctx *c) {
       f.mat = s.mat;
       f.GL = s.GL[ax];
       f.GR = s.GR[ax];
-      ader_status st = launch(c, s.face[ax], blocks_for((int64_t)s.g.nel[0] * s.nf), 0, &f, kBlock,
-                              s.g.nel[1], s.g.nel[2]);
+      const int fpb = face_per_block(s.D, s.N);
+      ader_status st = launch(c, s.face[ax], (s.g.nel[0] + fpb - 1) / fpb, 0, &f, kBlock, s.g.nel[1],
+                              s.g.nel[2]);
       if (st) return st;
     }
   }
@@ -365,7 +367,7 @@ ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
       a.GR[ax] = s.GR[ax];
     }
     a.u = u + s.u_off;
-    ader_status st = launch(c, s.ks.update, blocks_for((int64_t)s.g.nel[0] * s.m * s.nd), 0, &a, kBlock,
+    ader_status st = launch(c, s.update, blocks_for((int64_t)s.g.nel[0] * s.nd), 0, &a, kBlock,
                             s.g.nel[1], s.g.nel[2]);
     if (st) return st;
   }
@@ -504,20 +506,22 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
     s.trace_elt = d.prec == ADER_FP64 ? sizeof(double) : sizeof(float);
     s.face = d.prec == ADER_FP64 ? s.ks.face64 : s.ks.face32;
+    s.update = d.prec == ADER_FP64 ? s.ks.update64 : s.ks.update32;
     // candidate predictor variants: this precision, within the LDS budget;
     // for FP64 the HBM-accumulator variant only when no LDS variant fits
     std::vector<PredVariant> cand;
     const int want = d.prec == ADER_FP64 ? kFP64 : (d.prec == ADER_FP32 ? kFP32 : kBF16);
-    for (int pass = 0; pass < 2 && cand.empty(); pass++)
+    // preference: accumulator in LDS over HBM, then no scratch spills over spills
+    for (int pass = 0; pass < 4 && cand.empty(); pass++)
       for (int v = 0; v < s.ks.npred; v++) {
         const PredVariant &pv = s.ks.pred[v];
-        if (pv.prec != want || pv.lds > kLdsBytes || pv.acc_lds != (pass == 0)) continue;
+        if (pv.prec != want || pv.lds > kLdsBytes || pv.acc_lds != (pass < 2)) continue;
         hipFuncAttributes fa;
         if (hipFuncGetAttributes(&fa, pv.fn) != hipSuccess) {
           (void)hipGetLastError();
           continue;
         }
-        if (fa.localSizeBytes > 0) continue;  // register spills to scratch: never competitive
+        if ((fa.localSizeBytes > 0) != (pass % 2 == 1)) continue;
         if (hipFuncSetAttribute(pv.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pv.lds) !=
             hipSuccess) {
           (void)hipGetLastError();
@@ -543,7 +547,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     tune_list.push_back(tune ? cand : std::vector<PredVariant>());
     // device buffers
     const size_t ub = (size_t)s.u_cnt * sizeof(double);
-    const size_t gb = (size_t)s.E * s.m * s.nf * sizeof(double);
+    const size_t gb = (size_t)s.E * s.m * s.nf * s.trace_elt;  // face integrals share the trace type
     if ((st = dalloc(c, (void **)&s.ustar, ub))) return bail(st);
     const size_t tb = (size_t)s.u_cnt * s.trace_elt;
     for (int a = 0; a < s.D; a++) {

@@ -20,9 +20,10 @@ constexpr int kMaxVariants = 12;
 struct KernelSet {
   PredVariant pred[kMaxVariants];
   int npred = 0;
-  const void *face64[3] = {nullptr, nullptr, nullptr};  // FP64 traces
-  const void *face32[3] = {nullptr, nullptr, nullptr};  // FP32 traces
-  const void *update = nullptr;
+  const void *face64[3] = {nullptr, nullptr, nullptr};  // FP64 traces and face integrals
+  const void *face32[3] = {nullptr, nullptr, nullptr};  // FP32 traces and face integrals
+  const void *update64 = nullptr;                       // FP64 face integrals
+  const void *update32 = nullptr;                       // FP32 face integrals
   const void *cfl = nullptr;
   int M = 0, n = 0, ND = 0, NST = 0, NF = 0, ACC = 0;
 };
@@ -54,17 +55,18 @@ KernelSet make_kernel_set() {
   add_variant<D, N, PDE, kFP32, true, true, 2>(k, "fp32-mfma-b2");
   add_variant<D, N, PDE, kBF16, true, false, 1>(k, "bf16-valu-b1");
   add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
-  k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double>;
-  k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float>;
+  k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double, double>;
+  k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float, float>;
   if constexpr (D > 1) {
-    k.face64[1] = (const void *)&k_face<D, N, PDE, 1, double>;
-    k.face32[1] = (const void *)&k_face<D, N, PDE, 1, float>;
+    k.face64[1] = (const void *)&k_face<D, N, PDE, 1, double, double>;
+    k.face32[1] = (const void *)&k_face<D, N, PDE, 1, float, float>;
   }
   if constexpr (D > 2) {
-    k.face64[2] = (const void *)&k_face<D, N, PDE, 2, double>;
-    k.face32[2] = (const void *)&k_face<D, N, PDE, 2, float>;
+    k.face64[2] = (const void *)&k_face<D, N, PDE, 2, double, double>;
+    k.face32[2] = (const void *)&k_face<D, N, PDE, 2, float, float>;
   }
-  k.update = (const void *)&k_update<D, N, PDE>;
+  k.update64 = (const void *)&k_update<D, N, PDE, double>;
+  k.update32 = (const void *)&k_update<D, N, PDE, float>;
   k.cfl = (const void *)&k_cfl<D, N, PDE>;
   k.M = PDE::M;
   k.n = S::n;
