@@ -19,6 +19,7 @@ struct Ops {
   double V[kMaxN * kMaxN];   // volume operator V[k][j] = w_j phi_k'(xi_j) / w_k
   double F0[kMaxN], F1[kMaxN];  // phi_k(0), phi_k(1): face extrapolation
   double L0[kMaxN], L1[kMaxN];  // lifting phi_k(0)/w_k, phi_k(1)/w_k
+  double Trow[kMaxN];           // row sums of T (applied to a time-constant right-hand side)
 };
 
 // Host: build the tables of degree N (0..7).  Returns 0 on success.

@@ -8,6 +8,14 @@
 
 namespace ader {
 
+// Read-only operator tables: loads through the constant address space, so
+// that uniform indices become scalar loads even after the kernel has
+// written global memory (the tables are never written by a kernel).
+template <typename T>
+__device__ __forceinline__ T cload(const T *p) {
+  return *(const __attribute__((address_space(4))) T *)p;
+}
+
 // ------------------------------------------------------------ PDE systems
 
 // Compressible Euler equations (Sec. 3.1, eq. euler), ideal gas.
@@ -25,9 +33,17 @@ struct Elastic {
   static constexpr bool kElastic = true;
 };
 
-// 1/x: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32,
-// where the Picard sweeps are later corrected by an FP64 sweep.
-__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+// 1/x.  FP64: the hardware reciprocal estimate refined by two Newton-Raphson
+// steps r <- r + r (1 - x r) (each squares the relative error), which ends
+// within about one ulp of the correctly rounded quotient at a third of the
+// instructions of an IEEE division; x is a positive normal density here.
+// FP32: the hardware reciprocal (1 ulp), where the Picard sweeps are later
+// corrected by an FP64 sweep.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
+}
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Flux F_A(q) of the Euler equations; p = (gamma-1)(rho E - |rho v|^2/(2 rho)).
@@ -95,15 +111,25 @@ __device__ __forceinline__ void elastic_bg(const R *g, R irho, R lam, R mu, R *o
 // Precision modes of the predictor's Picard sweeps.
 enum Prec : int { kFP64 = 0, kFP32 = 1, kBF16 = 2 };
 
-// Float copies of the sweep operators (the FP32/BF16 sweeps use these).
-struct OpsF {
-  float D[kMaxN * kMaxN];
-  float T[kMaxN * kMaxN];
+// Sweep operators of one problem, FP64 and FP32 copies, read through a
+// device pointer (uniform addresses: scalar loads).  DA[A] = -(1/h_A) Dhat
+// carries the mesh width and sign of the axis-A term, so the contraction
+// accumulates straight into the right-hand side; T is the time operator and
+// Trow its row sums.
+struct OpsSweep {
+  double DA[3][kMaxN * kMaxN];
+  double T[kMaxN * kMaxN];
+  double Trow[kMaxN];
+  float DAf[3][kMaxN * kMaxN];
+  float Tf[kMaxN * kMaxN];
+  float Trowf[kMaxN];
+  float Df[kMaxN * kMaxN];   // unscaled Dhat (MFMA operands, scaled after the contraction)
+  double VA[3][kMaxN * kMaxN];  // (1/h_A) V: volume operator of axis A
 };
 
 struct PredArgs {
-  Ops ops;
-  OpsF opsf;
+  const OpsSweep *sw;   // sweep operators
+  const Ops *ops;     // device copy of all FP64 tables (outputs index them per lane)
   Geom g;
   const double *u;      // [E][M][ND]
   const double *dt;     // device scalar
@@ -152,18 +178,11 @@ __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
 }
 
 template <typename T>
-__device__ __forceinline__ T opD(const PredArgs &P, int i);
+__device__ __forceinline__ T opD(const PredArgs &P, int A, int i);
 template <>
-__device__ __forceinline__ double opD<double>(const PredArgs &P, int i) { return P.ops.D[i]; }
+__device__ __forceinline__ double opD<double>(const PredArgs &P, int A, int i) { return cload(&P.sw->DA[A][i]); }
 template <>
-__device__ __forceinline__ float opD<float>(const PredArgs &P, int i) { return P.opsf.D[i]; }
-template <typename T>
-__device__ __forceinline__ T opT(const PredArgs &P, int i);
-template <>
-__device__ __forceinline__ double opT<double>(const PredArgs &P, int i) { return P.ops.T[i]; }
-template <>
-__device__ __forceinline__ float opT<float>(const PredArgs &P, int i) { return P.opsf.T[i]; }
-
+__device__ __forceinline__ float opD<float>(const PredArgs &P, int A, int i) { return cload(&P.sw->DAf[A][i]); }
 // Round to the nearest bfloat16 (ties to even), kept in a float register.
 __device__ __forceinline__ float round_bf16(float x) {
   uint32_t b = __float_as_uint(x);
@@ -177,14 +196,14 @@ __device__ __forceinline__ float round_bf16(float x) {
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
 // Lines are enumerated over (l0, the other spatial indices).  With kRoundBF
 // the contraction inputs are rounded to bfloat16.
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS>
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kConst>
 __device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sacc, T irho, T lam,
                                          T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
-  const T ih = (T)P.g.inv_h[A];
-  for (int L = threadIdx.x; L < NST / n; L += BS) {
+  constexpr int NL = kConst ? NF : NST / n;  // a time-constant iterate: time slice 0 only
+  for (int L = threadIdx.x; L < NL; L += BS) {
     const int l0 = L / NF, r = L - l0 * NF;
     const int lo = r % ST, hi = r / ST;
     const int base = l0 * ND + lo + hi * ST * n;
@@ -193,7 +212,12 @@ __device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sac
     for (int j = 0; j < n; j++)
 #pragma unroll
       for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * NST + base + j * ST];
-    T out[n][M];
+    // the accumulated right-hand side of the earlier axes
+    T acc[n][M];
+#pragma unroll
+    for (int k = 0; k < n; k++)
+#pragma unroll
+      for (int v = 0; v < M; v++) acc[k][v] = A == 0 ? T(0) : sacc[v * NST + base + k * ST];
     if constexpr (!PDE::kElastic) {
       T F[n][M];
 #pragma unroll
@@ -206,12 +230,9 @@ __device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sac
 #pragma unroll
       for (int k = 0; k < n; k++)
 #pragma unroll
-        for (int v = 0; v < M; v++) {
-          T s = T(0);
+        for (int v = 0; v < M; v++)
 #pragma unroll
-          for (int j = 0; j < n; j++) s += opD<T>(P, k * kMaxN + j) * F[j][v];
-          out[k][v] = -s * ih;
-        }
+          for (int j = 0; j < n; j++) acc[k][v] += opD<T>(P, A, k * kMaxN + j) * F[j][v];
     } else {
       if constexpr (kRoundBF)
 #pragma unroll
@@ -225,22 +246,18 @@ __device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sac
         for (int v = 0; v < M; v++) {
           T s = T(0);
 #pragma unroll
-          for (int j = 0; j < n; j++) s += opD<T>(P, k * kMaxN + j) * qv[j][v];
+          for (int j = 0; j < n; j++) s += opD<T>(P, A, k * kMaxN + j) * qv[j][v];
           gk[v] = s;
         }
         elastic_bg<A, T>(gk, irho, lam, mu, bg);
 #pragma unroll
-        for (int v = 0; v < M; v++) out[k][v] = -bg[v] * ih;
+        for (int v = 0; v < M; v++) acc[k][v] += bg[v];
       }
     }
 #pragma unroll
     for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) {
-        const int idx = v * NST + base + k * ST;
-        if (A == 0) sacc[idx] = out[k][v];
-        else sacc[idx] += out[k][v];
-      }
+      for (int v = 0; v < M; v++) sacc[v * NST + base + k * ST] = acc[k][v];
   }
 }
 
@@ -254,7 +271,20 @@ struct TimeItems {
 // T, writing q as TO (may alias R: every thread reads its whole time line
 // before writing it back).  Thread tid owns the time lines tid + r*BS, whose
 // u values it keeps in ureg[r] across sweeps.
-template <int D, int N, class PDE, typename T, typename TO, int BS>
+template <typename T>
+__device__ __forceinline__ T opT(const PredArgs &P, int i);
+template <>
+__device__ __forceinline__ double opT<double>(const PredArgs &P, int i) { return cload(&P.sw->T[i]); }
+template <>
+__device__ __forceinline__ float opT<float>(const PredArgs &P, int i) { return cload(&P.sw->Tf[i]); }
+template <typename T>
+__device__ __forceinline__ T opTrow(const PredArgs &P, int l);
+template <>
+__device__ __forceinline__ double opTrow<double>(const PredArgs &P, int l) { return cload(&P.sw->Trow[l]); }
+template <>
+__device__ __forceinline__ float opTrow<float>(const PredArgs &P, int l) { return cload(&P.sw->Trowf[l]); }
+
+template <int D, int N, class PDE, typename T, typename TO, int BS, bool kConst>
 __device__ __forceinline__ void time_phase(const PredArgs &P, const T *sacc, TO *qout,
                                            const double *ureg, T dt) {
   using S = Shape<D, N>;
@@ -265,36 +295,47 @@ __device__ __forceinline__ void time_phase(const PredArgs &P, const T *sacc, TO 
     const int i = threadIdx.x + r * BS;
     if (i < M * ND) {
       const int v = i / ND, k = i - v * ND;
-      T rr[n];
-#pragma unroll
-      for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
       const T u0 = (T)ureg[r];
+      if constexpr (kConst) {
+        // R is the same at every time node: sum_j T[l][j] R = Trow[l] R
+        const T r0 = sacc[v * NST + k];
 #pragma unroll
-      for (int l = 0; l < n; l++) {
-        T a = T(0);
+        for (int l = 0; l < n; l++) qout[v * NST + l * ND + k] = (TO)(u0 + dt * (opTrow<T>(P, l) * r0));
+      } else {
+        T rr[n];
 #pragma unroll
-        for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
-        qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
+        for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
+#pragma unroll
+        for (int l = 0; l < n; l++) {
+          T a = T(0);
+#pragma unroll
+          for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
+          qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
+        }
       }
     }
   }
 }
 
-// One Picard sweep: R(q) over all axes, then the time contraction.
-template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS>
+// One Picard sweep: R(q) over all axes, then the time contraction.  With
+// kConst the iterate is constant in time (the first sweep from q^0 = u), so
+// R is evaluated on one time slice and the time operator reduces to its row
+// sums -- the same values as the full sweep up to rounding.
+template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS,
+          bool kConst = false>
 __device__ __forceinline__ void picard_sweep(const PredArgs &P, const TQ *sq, T *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu) {
-  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
   if constexpr (D > 1) {
-    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
   if constexpr (D > 2) {
-    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
-  time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
+  time_phase<D, N, PDE, T, TO, BS, kConst>(P, sacc, qout, ureg, dt);
   __syncthreads();
 }
 
@@ -454,7 +495,7 @@ __device__ __forceinline__ void euler_time_flux(const PredArgs &P, const double 
       double q[M], F[M];
 #pragma unroll
       for (int v = 0; v < M; v++) q[v] = qf[v * NST + l0 * ND + k];
-      const double wl = P.ops.w[l0];
+      const double wl = cload(&P.ops->w[l0]);
       euler_flux<D, 0, double>(q, gm1, F);
 #pragma unroll
       for (int v = 0; v < M; v++) fb[0][v] += wl * F[v];
@@ -476,29 +517,58 @@ __device__ __forceinline__ void euler_time_flux(const PredArgs &P, const double 
   }
 }
 
-// Euler volume term, step 2 (one thread per DOF), fused with u* = u + dt V:
-//   V(v,k) = sum_A (1/h_A) sum_j Vop[k_A][j] FB[A][v][k with k_A = j]
-template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void euler_volume_update(const PredArgs &P, const double *FB, const double *ue,
-                                                    double *us, double dt) {
+// Work split of an output phase over ITEMS independent items (lines or
+// nodes) and the M variables: VG groups of VPG variables, so that up to
+// ITEMS*VG threads of the block have work and the index arithmetic of an
+// item is done once for all its variables.
+template <int ITEMS, int M, int BS>
+struct Split {
+  static constexpr int VG = BS / ITEMS < 1 ? 1 : (BS / ITEMS > M ? M : BS / ITEMS);
+  static constexpr int VPG = (M + VG - 1) / VG;
+};
+
+// Euler volume term, step 2, for axis A (one thread per line of axis A and
+// variable group):  V(v,k) += (1/h_A) sum_j Vop[k_A][j] FB[A][v](k_A = j).
+// V accumulates in place of FB[0] (the axis-0 pass reads each line before it
+// overwrites it).
+template <int D, int N, class PDE, int A, int BS>
+__device__ __forceinline__ void euler_volume_axis(const PredArgs &P, double *FB) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND;
-  for (int i = threadIdx.x; i < M * ND; i += BS) {
-    const int v = i / ND, k = i - v * ND;
-    double V = 0.0;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
+  constexpr int ST = ipow(n, A);
+  using SP = Split<NF, M, BS>;
+  for (int it = threadIdx.x; it < NF * SP::VG; it += BS) {
+    const int g = it / NF, t = it - g * NF;
+    const int base = t % ST + (t / ST) * ST * n;
 #pragma unroll
-    for (int a = 0; a < D; a++) {
-      const int st = ipow(n, a);
-      const int ka = (k / st) % n;
-      const double *line = FB + (a * M + v) * ND + (k - ka * st);
-      double s = 0.0;
+    for (int vv = 0; vv < SP::VPG; vv++) {
+      const int v = g * SP::VPG + vv;
+      if (v < M) {
+        const double *src = FB + (A * M + v) * ND + base;
+        double *dst = FB + v * ND + base;
+        double f[n], acc[n];
 #pragma unroll
-      for (int j = 0; j < n; j++) s += P.ops.V[ka * kMaxN + j] * line[j * st];
-      V += s * P.g.inv_h[a];
+        for (int j = 0; j < n; j++) f[j] = src[j * ST];
+#pragma unroll
+        for (int k = 0; k < n; k++) acc[k] = A == 0 ? 0.0 : dst[k * ST];
+#pragma unroll
+        for (int k = 0; k < n; k++)
+#pragma unroll
+          for (int j = 0; j < n; j++) acc[k] += cload(&P.sw->VA[A][k * kMaxN + j]) * f[j];
+#pragma unroll
+        for (int k = 0; k < n; k++) dst[k * ST] = acc[k];
+      }
     }
-    // dt = 0 (flagged state or t already at t_end) leaves the state untouched
-    us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V;
   }
+}
+
+// u* = u + dt V from the accumulated volume term V[v][k] (one thread per DOF).
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void ustar_update(const double *V, const double *ue, double *us, double dt) {
+  constexpr int M = PDE::M, ND = Shape<D, N>::ND;
+  for (int i = threadIdx.x; i < M * ND; i += BS)
+    // dt = 0 (flagged state or t already at t_end) leaves the state untouched
+    us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V[i];
 }
 
 // Elastic volume term (one thread per node), fused with u* = u + dt V:
@@ -523,7 +593,7 @@ __device__ __forceinline__ void elastic_volume_update(const PredArgs &P, const d
       for (int v = 0; v < M; v++) {
         double s = 0.0;
 #pragma unroll
-        for (int j = 0; j < n; j++) s += P.ops.D[ka * kMaxN + j] * base[v * ND + j * st];
+        for (int j = 0; j < n; j++) s += cload(&P.ops->D[ka * kMaxN + j]) * base[v * ND + j * st];
         g[v] = s;
       }
       elastic_bg<A, double>(g, irho, lam, mu, bg);
@@ -543,28 +613,36 @@ __device__ __forceinline__ void elastic_volume_update(const PredArgs &P, const d
 
 // Boundary-extrapolated traces on both faces normal to axis A:
 // trace_s(v, l0, face node) = sum_j phi_j(s) q(v, l0, node with k_A = j),
-// computed in FP64 and stored as TT.
+// computed in FP64 and stored as TT.  One thread per (l0, face node) pair
+// and variable group; consecutive threads store consecutive trace values.
 template <int D, int N, class PDE, int A, typename TT, int BS>
 __device__ __forceinline__ void traces_axis(const PredArgs &P, const double *sq, int64_t e) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
+  using SP = Split<ND, M, BS>;
   TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(M * ND);
   TT *t1 = (TT *)P.trace[A][1] + e * (int64_t)(M * ND);
-  for (int i = threadIdx.x; i < M * ND; i += BS) {
-    const int v = i / ND, r = i - v * ND;
-    const int l0 = r / NF, kf = r - l0 * NF;
-    const int lo = kf % ST, hi = kf / ST;
-    const double *line = sq + v * NST + l0 * ND + lo + hi * ST * n;
-    double a0 = 0.0, a1 = 0.0;
+  for (int it = threadIdx.x; it < ND * SP::VG; it += BS) {
+    const int g = it / ND, t = it - g * ND;  // t = l0 * NF + kf
+    const int l0 = t / NF, kf = t - l0 * NF;
+    const int base = l0 * ND + kf % ST + (kf / ST) * ST * n;
 #pragma unroll
-    for (int j = 0; j < n; j++) {
-      const double qj = line[j * ST];
-      a0 += P.ops.F0[j] * qj;
-      a1 += P.ops.F1[j] * qj;
+    for (int vv = 0; vv < SP::VPG; vv++) {
+      const int v = g * SP::VPG + vv;
+      if (v < M) {
+        const double *line = sq + v * NST + base;
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; j++) {
+          const double qj = line[j * ST];
+          a0 += cload(&P.ops->F0[j]) * qj;
+          a1 += cload(&P.ops->F1[j]) * qj;
+        }
+        t0[v * ND + t] = (TT)a0;
+        t1[v * ND + t] = (TT)a1;
+      }
     }
-    t0[i] = (TT)a0;
-    t1[i] = (TT)a1;
   }
 }
 
@@ -590,13 +668,23 @@ __device__ __forceinline__ void predictor_outputs(const PredArgs &P, const doubl
   } else if constexpr (!PDE::kElastic) {
     euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
     __syncthreads();
-    euler_volume_update<D, N, PDE, BS>(P, scratch, ue, us, dt);
+    euler_volume_axis<D, N, PDE, 0, BS>(P, scratch);
+    __syncthreads();
+    if constexpr (D > 1) {
+      euler_volume_axis<D, N, PDE, 1, BS>(P, scratch);
+      __syncthreads();
+    }
+    if constexpr (D > 2) {
+      euler_volume_axis<D, N, PDE, 2, BS>(P, scratch);
+      __syncthreads();
+    }
+    ustar_update<D, N, PDE, BS>(scratch, ue, us, dt);
   } else {
     for (int i = threadIdx.x; i < M * ND; i += BS) {
       const int v = i / ND, k = i - v * ND;
       double a = 0.0;
 #pragma unroll
-      for (int l = 0; l < n; l++) a += P.ops.w[l] * qf[v * NST + l * ND + k];
+      for (int l = 0; l < n; l++) a += cload(&P.ops->w[l]) * qf[v * NST + l * ND + k];
       scratch[i] = a;
     }
     __syncthreads();
@@ -646,7 +734,9 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const Pre
       for (int l0 = 0; l0 < n; l0++) sq[v * NST + l0 * ND + k] = val;
     }
     __syncthreads();
-    for (int s = 0; s < P.sweeps; s++)
+    // the first sweep starts from the time-constant iterate q^0 = u
+    picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+    for (int s = 1; s < P.sweeps; s++)
       picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
     predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, dt, e, irho, lam, mu);
   } else {
@@ -671,14 +761,19 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const Pre
 #pragma unroll
         for (int j = 0; j < n; j++) {
           const int k = 4 * c + lq;
-          Db[c][j] = k < n ? P.opsf.D[k * kMaxN + j] : 0.f;
-          Tb[c][j] = k < n ? P.opsf.T[k * kMaxN + j] : 0.f;
+          Db[c][j] = k < n ? cload(&P.sw->Df[k * kMaxN + j]) : 0.f;
+          Tb[c][j] = k < n ? cload(&P.sw->Tf[k * kMaxN + j]) : 0.f;
         }
-      for (int s = 0; s + 1 < P.sweeps; s++)
-        picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db,
-                                         Tb);
+      if (P.sweeps > 1)  // first sweep from the time-constant iterate q^0 = u
+        picard_sweep<D, N, PDE, float, float, float, false, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                      (float)irho, (float)lam, (float)mu);
+      for (int s = 1; s + 1 < P.sweeps; s++)
+        picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
     } else {
-      for (int s = 0; s + 1 < P.sweeps; s++)
+      if (P.sweeps > 1)  // first sweep from the time-constant iterate q^0 = u
+        picard_sweep<D, N, PDE, float, float, float, kBF, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                    (float)irho, (float)lam, (float)mu);
+      for (int s = 1; s + 1 < P.sweeps; s++)
         picard_sweep<D, N, PDE, float, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho,
                                                           (float)lam, (float)mu);
     }
@@ -692,7 +787,7 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const Pre
 // ------------------------------------------------------------ faces
 
 struct FaceArgs {
-  Ops ops;
+  const Ops *ops;
   Geom g;
   const void *trace0;  // side-0 traces of axis A (the + neighbour reads these)
   const void *trace1;  // side-1 traces of axis A
@@ -742,7 +837,7 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
       qm[v] = (double)tm[v * n * NF];
       qp[v] = (double)tp[v * n * NF];
     }
-    const double wl = F.ops.w[l0];
+    const double wl = cload(&F.ops->w[l0]);
     if constexpr (!PDE::kElastic) {
       const double gamma = F.g.gamma;
       double Fm[M], Fp[M];
@@ -798,7 +893,7 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
 // ------------------------------------------------------------ update
 
 struct UpdArgs {
-  Ops ops;
+  const Ops *ops;
   Geom g;
   const double *ustar;
   const double *dt;
@@ -833,9 +928,9 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
     const int64_t eL = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
     gp[A] = (const GT *)U.GL[A] + e * (M * NF) + kf;
     gm[A] = (const GT *)(PDE::kConservative ? U.GL[A] : U.GR[A]) + eL * (M * NF) + kf;
-    cp[A] = U.g.inv_h[A] * U.ops.L1[ka];
+    cp[A] = U.g.inv_h[A] * cload(&U.ops->L1[ka]);
     // the - face: conservative systems use -G of the face owned by eL
-    cm[A] = PDE::kConservative ? -U.g.inv_h[A] * U.ops.L0[ka] : U.g.inv_h[A] * U.ops.L0[ka];
+    cm[A] = PDE::kConservative ? -U.g.inv_h[A] * cload(&U.ops->L0[ka]) : U.g.inv_h[A] * cload(&U.ops->L0[ka]);
   }
   const double dt = *U.dt;
   const int64_t base = e * (M * ND) + k;

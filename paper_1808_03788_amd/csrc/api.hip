@@ -36,7 +36,9 @@ struct ProbState {
   double tune_ms = 0.0;             // measured time of the chosen variant on the sample
   const void *const *face = nullptr;  // face entries for the trace type
   size_t trace_elt = 8;             // bytes per trace value
-  OpsF opsf{};
+  OpsSweep sw{};            // sweep operators (host copy)
+  OpsSweep *sw_dev = nullptr;  // device copy read by the predictor
+  Ops *ops_dev = nullptr;   // device copy of the tables (outputs, faces, update read them by pointer)
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
   void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};  // trace type
@@ -217,8 +219,8 @@ std::map<std::string, std::string> g_tune_cache;  // configuration -> variant na
 
 PredArgs pred_args(ProbState &s, const double *u, const double *dt, double *qhat) {
   PredArgs a{};
-  a.ops = s.ops;
-  a.opsf = s.opsf;
+  a.sw = s.sw_dev;
+  a.ops = s.ops_dev;
   a.g = s.g;
   a.u = u;
   a.dt = dt;
@@ -338,7 +340,7 @@ ader_status run_faces(ader_ctx *c) {
     ProbState &s = c->P[p];
     for (int ax = 0; ax < s.D; ax++) {
       FaceArgs f{};
-      f.ops = s.ops;
+      f.ops = s.ops_dev;
       f.g = s.g;
       f.trace0 = s.trace[ax][0];
       f.trace1 = s.trace[ax][1];
@@ -358,7 +360,7 @@ ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
   for (size_t p = 0; p < c->P.size(); p++) {
     ProbState &s = c->P[p];
     UpdArgs a{};
-    a.ops = s.ops;
+    a.ops = s.ops_dev;
     a.g = s.g;
     a.ustar = s.ustar;
     a.dt = (dt_dev ? dt_dev : c->dt) + p;
@@ -500,8 +502,18 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     qoff += s.q_cnt;
     moff += s.m;
     for (int k = 0; k < kMaxN * kMaxN; k++) {
-      s.opsf.D[k] = (float)s.ops.D[k];
-      s.opsf.T[k] = (float)s.ops.T[k];
+      for (int a = 0; a < 3; a++) {
+        s.sw.DA[a][k] = -s.g.inv_h[a] * s.ops.D[k];
+        s.sw.DAf[a][k] = (float)s.sw.DA[a][k];
+      }
+      s.sw.T[k] = s.ops.T[k];
+      s.sw.Tf[k] = (float)s.ops.T[k];
+      s.sw.Df[k] = (float)s.ops.D[k];
+      for (int a = 0; a < 3; a++) s.sw.VA[a][k] = s.g.inv_h[a] * s.ops.V[k];
+    }
+    for (int k = 0; k < kMaxN; k++) {
+      s.sw.Trow[k] = s.ops.Trow[k];
+      s.sw.Trowf[k] = (float)s.ops.Trow[k];
     }
     const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
     s.trace_elt = d.prec == ADER_FP64 ? sizeof(double) : sizeof(float);
@@ -546,6 +558,13 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     const bool tune = !forced && cand.size() > 1 && !(tune_env && strcmp(tune_env, "0") == 0);
     tune_list.push_back(tune ? cand : std::vector<PredVariant>());
     // device buffers
+    if ((st = dalloc(c, (void **)&s.ops_dev, sizeof(Ops)))) return bail(st);
+    if ((st = dalloc(c, (void **)&s.sw_dev, sizeof(OpsSweep)))) return bail(st);
+    if (hipMemcpy(s.ops_dev, &s.ops, sizeof(Ops), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s.sw_dev, &s.sw, sizeof(OpsSweep), hipMemcpyHostToDevice) != hipSuccess) {
+      c->msg = "operator table upload failed";
+      return bail(ADER_ERR_DEVICE);
+    }
     const size_t ub = (size_t)s.u_cnt * sizeof(double);
     const size_t gb = (size_t)s.E * s.m * s.nf * s.trace_elt;  // face integrals share the trace type
     if ((st = dalloc(c, (void **)&s.ustar, ub))) return bail(st);

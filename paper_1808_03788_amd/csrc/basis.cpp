@@ -169,6 +169,9 @@ int build_ops(int N, Ops *o) {
   for (int k = 0; k < n; k++) {
     o->L0[k] = o->F0[k] / o->w[k];
     o->L1[k] = o->F1[k] / o->w[k];
+    double r = 0.0;
+    for (int j = 0; j < n; j++) r += o->T[k * kMaxN + j];
+    o->Trow[k] = r;
   }
   return 0;
 }
