@@ -83,7 +83,11 @@ typedef struct {
  * share nothing but the stream).  `hip_stream` is a hipStream_t (NULL = the
  * default stream).  Device memory for traces, face integrals and the
  * predictor's output is allocated here and owned by the context.  The
- * simulation time of every problem starts at 0. */
+ * simulation time of every problem starts at 0.  Problems of equal
+ * dimension, degree, PDE and precision form one kernel class: every stage
+ * of a step is one launch per class over the elements of all its problems
+ * (persistent workgroups walking per-problem tile ranges held in device
+ * memory), so the launch count of a step does not grow with nprob. */
 ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stream,
                         ader_ctx **out);
 /* Free everything the context owns.  NULL is accepted. */
@@ -129,6 +133,15 @@ ader_status ader_corrector(ader_ctx *ctx, double *u, const double *dt_dev);
  * predictor, corrector, time advance.  Host-synchronisation free, so it can
  * be captured into a hipGraph (the captured t_end values are then fixed). */
 ader_status ader_step(ader_ctx *ctx, double *u, const double *t_end_host);
+
+/* nsteps consecutive ader_step calls replayed as one HIP graph.  The graph
+ * is captured on the first call (and again when u or nsteps change) on a
+ * stream of the context's own, ordered after earlier work on the context
+ * stream; later work on that stream waits for the replay.  Results are
+ * bitwise those of nsteps ader_step calls.  Stage profiling does not apply
+ * to replays.  nsteps >= 1, else ADER_ERR_INVALID.  Changing t_end_host
+ * between calls costs one synchronous copy. */
+ader_status ader_run(ader_ctx *ctx, double *u, const double *t_end_host, int32_t nsteps);
 
 /* Current simulation time of every problem (host [nprob]); synchronises and
  * reports a latched ADER_ERR_NONFINITE. */

@@ -27,7 +27,7 @@ EXPORTS = [
     "ader_predictor", "ader_qhat_layout", "ader_corrector", "ader_step", "ader_time",
     "ader_set_time", "ader_last_dt", "ader_totals", "ader_last_error",
     "ader_stability_alpha", "ader_basis", "ader_version", "ader_profile", "ader_stage_times",
-    "ader_describe",
+    "ader_describe", "ader_run",
 ]
 
 
@@ -68,6 +68,7 @@ def lib():
         L.ader_predictor.argtypes = [_VP, _VP, _VP, _VP]
         L.ader_corrector.argtypes = [_VP, _VP, _VP]
         L.ader_step.argtypes = [_VP, _VP, _DP]
+        L.ader_run.argtypes = [_VP, _VP, _DP, C.c_int32]
         L.ader_time.argtypes = [_VP, _DP]
         L.ader_set_time.argtypes = [_VP, _DP]
         L.ader_last_dt.argtypes = [_VP, _DP]
@@ -199,6 +200,11 @@ def ader_corrector(ctx: int, u, dt_dev=None):
 def ader_step(ctx: int, u, t_end: Sequence[float]):
     te = np.ascontiguousarray(t_end, dtype=np.float64)
     _check(lib().ader_step(_VP(ctx), _VP(_ptr(u)), te.ctypes.data_as(_DP)), ctx)
+
+
+def ader_run(ctx: int, u, t_end: Sequence[float], nsteps: int):
+    te = np.ascontiguousarray(t_end, dtype=np.float64)
+    _check(lib().ader_run(_VP(ctx), _VP(_ptr(u)), te.ctypes.data_as(_DP), int(nsteps)), ctx)
 
 
 def ader_time(ctx: int, nprob: int) -> np.ndarray:
@@ -333,6 +339,12 @@ class Context:
         if np.isscalar(t_end):
             t_end = [t_end] * self.nprob
         ader_step(self.ctx, u, t_end)
+
+    def run(self, u, t_end, nsteps):
+        """nsteps steps replayed as one captured HIP graph."""
+        if np.isscalar(t_end):
+            t_end = [t_end] * self.nprob
+        ader_run(self.ctx, u, t_end, nsteps)
 
     def time(self):
         return ader_time(self.ctx, self.nprob)

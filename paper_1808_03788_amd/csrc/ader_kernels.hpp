@@ -13,7 +13,47 @@ namespace ader {
 // written global memory (the tables are never written by a kernel).
 template <typename T>
 __device__ __forceinline__ T cload(const T *p) {
-  return *(const __attribute__((address_space(4))) T *)p;
+  if constexpr (__is_arithmetic(T) || __is_pointer(T)) {
+    return *(const __attribute__((address_space(4))) T *)p;
+  } else {  // argument records: copied word by word
+    static_assert(sizeof(T) % 4 == 0, "record size");
+    T out;
+    const __attribute__((address_space(4))) uint32_t *src = (const __attribute__((address_space(4))) uint32_t *)p;
+    uint32_t *dst = (uint32_t *)&out;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); i++) dst[i] = src[i];
+    return out;
+  }
+}
+
+// Tiles of a batched launch.  Problem p of the batch owns the tiles
+// [start[p], start[p+1]); a kernel walks the tiles start[0]..start[np]-1
+// with a grid-stride loop (persistent workgroups), so one launch covers any
+// number of problems of one kernel class.
+struct Batch {
+  const int64_t *start;  // device [np + 1]
+  int np;
+};
+
+// Row-chunk tiles of the face and update kernels, listed explicitly: the
+// problem and the chunk's (x-chunk, y, z) position.  A table read replaces
+// the search and the integer divisions of the decomposition.
+struct RowTile {
+  int p;     // problem within the launch's argument records
+  int pidx;  // problem index in the context (its dt)
+  int bx;    // chunk along the x-row
+  int yz;    // iy | iz << 16
+};
+
+// The problem that owns `tile` (uniform: binary search on scalar loads).
+__device__ __forceinline__ int tile_problem(const Batch &b, int64_t tile) {
+  int lo = 0, hi = b.np - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (cload(&b.start[mid]) <= tile) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
 }
 
 // ------------------------------------------------------------ PDE systems
@@ -131,16 +171,20 @@ struct PredArgs {
   const OpsSweep *sw;   // sweep operators
   const Ops *ops;     // device copy of all FP64 tables (outputs index them per lane)
   Geom g;
-  const double *u;      // [E][M][ND]
-  const double *dt;     // device scalar
+  int64_t u_off;        // offset of the problem's u[E][M][ND] in the state buffer
+  int64_t q_off;        // offset of its q-hat in the optional q-hat buffer
+  int pidx;             // problem index: its time step is dt[pidx]
   const double *mat;    // elastic: [E][3]
   double *ustar;        // [E][M][ND]  u + dt * volume terms
   void *trace[3][2];    // [E][M][n][ND/n] per axis and side (0: x_A = 0, 1: x_A = 1);
                         // double for FP64, float for the mixed modes
-  double *qhat;         // optional [E][M][n][ND]
   double *acc_glob;     // FP64 accumulator when it does not fit in LDS: [E][M][ACC]
   int sweeps;
 };
+// Argument records are read in place through the constant address space:
+// every field load is a scalar load, whatever the kernel has written.
+using PArg = const __attribute__((address_space(4))) PredArgs;
+
 
 template <int D, int N>
 struct Shape {
@@ -178,11 +222,11 @@ __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
 }
 
 template <typename T>
-__device__ __forceinline__ T opD(const PredArgs &P, int A, int i);
+__device__ __forceinline__ T opD(PArg &P, int A, int i);
 template <>
-__device__ __forceinline__ double opD<double>(const PredArgs &P, int A, int i) { return cload(&P.sw->DA[A][i]); }
+__device__ __forceinline__ double opD<double>(PArg &P, int A, int i) { return cload(&P.sw->DA[A][i]); }
 template <>
-__device__ __forceinline__ float opD<float>(const PredArgs &P, int A, int i) { return cload(&P.sw->DAf[A][i]); }
+__device__ __forceinline__ float opD<float>(PArg &P, int A, int i) { return cload(&P.sw->DAf[A][i]); }
 // Round to the nearest bfloat16 (ties to even), kept in a float register.
 __device__ __forceinline__ float round_bf16(float x) {
   uint32_t b = __float_as_uint(x);
@@ -197,7 +241,7 @@ __device__ __forceinline__ float round_bf16(float x) {
 // Lines are enumerated over (l0, the other spatial indices).  With kRoundBF
 // the contraction inputs are rounded to bfloat16.
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kConst>
-__device__ __forceinline__ void rhs_axis(const PredArgs &P, const TQ *sq, T *sacc, T irho, T lam,
+__device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam,
                                          T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
@@ -272,20 +316,20 @@ struct TimeItems {
 // before writing it back).  Thread tid owns the time lines tid + r*BS, whose
 // u values it keeps in ureg[r] across sweeps.
 template <typename T>
-__device__ __forceinline__ T opT(const PredArgs &P, int i);
+__device__ __forceinline__ T opT(PArg &P, int i);
 template <>
-__device__ __forceinline__ double opT<double>(const PredArgs &P, int i) { return cload(&P.sw->T[i]); }
+__device__ __forceinline__ double opT<double>(PArg &P, int i) { return cload(&P.sw->T[i]); }
 template <>
-__device__ __forceinline__ float opT<float>(const PredArgs &P, int i) { return cload(&P.sw->Tf[i]); }
+__device__ __forceinline__ float opT<float>(PArg &P, int i) { return cload(&P.sw->Tf[i]); }
 template <typename T>
-__device__ __forceinline__ T opTrow(const PredArgs &P, int l);
+__device__ __forceinline__ T opTrow(PArg &P, int l);
 template <>
-__device__ __forceinline__ double opTrow<double>(const PredArgs &P, int l) { return cload(&P.sw->Trow[l]); }
+__device__ __forceinline__ double opTrow<double>(PArg &P, int l) { return cload(&P.sw->Trow[l]); }
 template <>
-__device__ __forceinline__ float opTrow<float>(const PredArgs &P, int l) { return cload(&P.sw->Trowf[l]); }
+__device__ __forceinline__ float opTrow<float>(PArg &P, int l) { return cload(&P.sw->Trowf[l]); }
 
 template <int D, int N, class PDE, typename T, typename TO, int BS, bool kConst>
-__device__ __forceinline__ void time_phase(const PredArgs &P, const T *sacc, TO *qout,
+__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout,
                                            const double *ureg, T dt) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
@@ -323,7 +367,7 @@ __device__ __forceinline__ void time_phase(const PredArgs &P, const T *sacc, TO 
 // sums -- the same values as the full sweep up to rounding.
 template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS,
           bool kConst = false>
-__device__ __forceinline__ void picard_sweep(const PredArgs &P, const TQ *sq, T *sacc, TO *qout,
+__device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu) {
   rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
@@ -361,7 +405,7 @@ __device__ __forceinline__ int line_base(int line, int ST) {
 }
 
 template <int D, int N, class PDE, int A, int BS>
-__device__ __forceinline__ void rhs_axis_mfma(const PredArgs &P, const float *sq, float *sacc,
+__device__ __forceinline__ void rhs_axis_mfma(PArg &P, const float *sq, float *sacc,
                                               const float (&Da)[2][N + 1], float irho, float lam,
                                               float mu) {
   using S = Shape<D, N>;
@@ -461,7 +505,7 @@ __device__ __forceinline__ void time_phase_mfma(const float *sacc, float *sq, co
 }
 
 template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void picard_sweep_mfma(const PredArgs &P, float *sq, float *sacc, const double *ureg,
+__device__ __forceinline__ void picard_sweep_mfma(PArg &P, float *sq, float *sacc, const double *ureg,
                                                   float dt, float irho, float lam, float mu,
                                                   const float (&Da)[2][N + 1], const float (&Ta)[2][N + 1]) {
   rhs_axis_mfma<D, N, PDE, 0, BS>(P, sq, sacc, Da, irho, lam, mu);
@@ -481,7 +525,7 @@ __device__ __forceinline__ void picard_sweep_mfma(const PredArgs &P, float *sq, 
 // Euler volume term, step 1: time-integrated flux of every axis at every
 // spatial node, FB[A][v][k] = sum_l0 w_l0 F_A(q(l0,k)) (one thread per node).
 template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void euler_time_flux(const PredArgs &P, const double *qf, double *FB) {
+__device__ __forceinline__ void euler_time_flux(PArg &P, const double *qf, double *FB) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   const double gm1 = P.g.gamma - 1.0;
@@ -532,7 +576,7 @@ struct Split {
 // V accumulates in place of FB[0] (the axis-0 pass reads each line before it
 // overwrites it).
 template <int D, int N, class PDE, int A, int BS>
-__device__ __forceinline__ void euler_volume_axis(const PredArgs &P, double *FB) {
+__device__ __forceinline__ void euler_volume_axis(PArg &P, double *FB) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
   constexpr int ST = ipow(n, A);
@@ -574,7 +618,7 @@ __device__ __forceinline__ void ustar_update(const double *V, const double *ue, 
 // Elastic volume term (one thread per node), fused with u* = u + dt V:
 //   V = -sum_A (1/h_A) B_A Dhat_A qbar,  qbar = sum_l0 w_l0 q(l0)  (B constant in the element)
 template <int D, int N, int BS>
-__device__ __forceinline__ void elastic_volume_update(const PredArgs &P, const double *QB, const double *ue,
+__device__ __forceinline__ void elastic_volume_update(PArg &P, const double *QB, const double *ue,
                                                       double *us, double dt, double irho, double lam,
                                                       double mu) {
   using S = Shape<D, N>;
@@ -616,7 +660,7 @@ __device__ __forceinline__ void elastic_volume_update(const PredArgs &P, const d
 // computed in FP64 and stored as TT.  One thread per (l0, face node) pair
 // and variable group; consecutive threads store consecutive trace values.
 template <int D, int N, class PDE, int A, typename TT, int BS>
-__device__ __forceinline__ void traces_axis(const PredArgs &P, const double *sq, int64_t e) {
+__device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
@@ -650,15 +694,13 @@ __device__ __forceinline__ void traces_axis(const PredArgs &P, const double *sq,
 // face traces, the volume terms (scratch of D*M*ND doubles) and
 // u* = u + dt V.
 template <int D, int N, class PDE, typename TT, int BS>
-__device__ __forceinline__ void predictor_outputs(const PredArgs &P, const double *qf, double *scratch,
-                                                  const double *ue, double dt, int64_t e, double irho,
-                                                  double lam, double mu) {
+__device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, double *scratch,
+                                                  const double *ue, double dt, int64_t e, double *qo,
+                                                  double irho, double lam, double mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
-  if (P.qhat) {
-    double *qo = P.qhat + e * (int64_t)(M * NST);
+  if (qo)
     for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
-  }
   traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
   if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
   if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
@@ -701,15 +743,12 @@ __device__ __forceinline__ void predictor_outputs(const PredArgs &P, const doubl
 //  kMfma: the FP32 sweeps contract on MFMA instead of VALU FMAs.
 //  kBFac: block-size factor (threads = pred_block(D, N, kBFac)).
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
-__global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const PredArgs P) {
+__device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const double *ue, double dt,
+                                                  double *qo, unsigned char *smem_raw) {
   constexpr int BS = pred_block(D, N, kBFac);
   using S = Shape<D, N>;
   using L = PredLds<D, N, PDE::M, PREC>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int64_t e = blockIdx.x;
-  const double *ue = P.u + e * (int64_t)(M * ND);
-  const double dt = *P.dt;
   double irho = 0.0, lam = 0.0, mu = 0.0;
   if constexpr (PDE::kElastic) {
     irho = 1.0 / P.mat[3 * e + 0];
@@ -738,7 +777,7 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const Pre
     picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
     for (int s = 1; s < P.sweeps; s++)
       picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, dt, e, irho, lam, mu);
+    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, dt, e, qo, irho, lam, mu);
   } else {
     constexpr bool kBF = PREC == kBF16;
     float *sq32 = (float *)smem_raw;
@@ -780,8 +819,28 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac)) k_predictor(const Pre
     // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
     // the FP64 accumulator in place
     picard_sweep<D, N, PDE, double, float, double, false, BS>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, dt, e, irho, lam, mu);
+    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, dt, e, qo, irho, lam, mu);
   }
+}
+
+// Batched predictor: workgroup b owns tile b, one element of one problem of
+// the batch (one launch per kernel class; the grid is the total tile count).
+// A grid-stride loop over tiles would let the compiler keep every per-thread
+// index of the element phases live across iterations and cost occupancy, so
+// each workgroup takes a single element.  u, dt and the optional q-hat output
+// are the call's buffers (per-problem offsets in the record).
+template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
+__global__ void __launch_bounds__(pred_block(D, N, kBFac))
+    k_predictor(const PredArgs *args, const Batch b, const double *u, const double *dt, double *qhat) {
+  constexpr int M = PDE::M, ND = Shape<D, N>::ND, NST = Shape<D, N>::NST;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t tile = blockIdx.x;
+  const int p = tile_problem(b, tile);
+  PArg &P = *(PArg *)&args[p];
+  const int64_t e = tile - cload(&b.start[p]);
+  const double *ue = u + P.u_off + e * (int64_t)(M * ND);
+  double *qo = qhat ? qhat + P.q_off + e * (int64_t)(M * NST) : nullptr;
+  predictor_element<D, N, PDE, PREC, kAccLds, kMfma, kBFac>(P, e, ue, cload(&dt[P.pidx]), qo, smem_raw);
 }
 
 // ------------------------------------------------------------ faces
@@ -794,6 +853,7 @@ struct FaceArgs {
   const double *mat;
   void *GL;            // [E][M][NF] face integral for the element on the - side (GT)
   void *GR;            // [E][M][NF] for the element on the + side (non-conservative only)
+  int cx;              // x-chunks of face_per_block faces per x-row
 };
 
 // Faces handled by one workgroup of the face kernel: as many whole faces as
@@ -807,22 +867,21 @@ __host__ __device__ constexpr int face_per_block(int D, int N) {
 // neighbour (side 0), integrated in time with the GL weights, in FP64 from
 // traces stored as TT, stored as GT.  One thread per (face, time node, face node), so that
 // consecutive threads read consecutive trace values; the time integral is
-// summed through LDS in time-node order.  Grid: (x-row chunks of FPB faces,
-// ny, nz), so element coordinates need no division.
+// summed through LDS in time-node order.  A tile is chunk bx of FPB faces of
+// the x-row (iy, iz).
 template <int D, int N, class PDE, int A, typename TT, typename GT>
-__global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
+__device__ __forceinline__ void face_tile(const FaceArgs &F, int bx, int iy, int iz, double *sDraw) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
   constexpr int FPB = face_per_block(D, N);
   constexpr int NI = FPB * n * NF;            // (face, l0, kf) items of the block
   constexpr int NG = PDE::kConservative ? 1 : 2;
-  __shared__ double sD[NG][FPB][M][n * NF];  // w_l0 * D^-(l0, kf) per face
+  double(*sD)[FPB][M][n * NF] = (double(*)[FPB][M][n * NF])sDraw;  // w_l0 * D^-(l0, kf) per face
   const int nx = F.g.nel[0], ny = F.g.nel[1], nz = F.g.nel[2];
-  const int iy = blockIdx.y, iz = blockIdx.z;
   for (int it = threadIdx.x; it < NI; it += kBlock) {
     const int f = it / (n * NF), r = it - f * (n * NF);  // r = l0 * NF + kf
     const int l0 = r / NF, kf = r - l0 * NF;
-    const int ix = blockIdx.x * FPB + f;
+    const int ix = bx * FPB + f;
     if (ix >= nx) continue;
     const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
     const int jx = (A == 0) ? (ix + 1 == nx ? 0 : ix + 1) : ix;
@@ -877,7 +936,7 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
   for (int it = threadIdx.x; it < FPB * M * NF; it += kBlock) {
     const int f = it / (M * NF), r = it - f * (M * NF);
     const int v = r / NF, kf = r - v * NF;
-    const int ix = blockIdx.x * FPB + f;
+    const int ix = bx * FPB + f;
     if (ix >= nx) continue;
     const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
 #pragma unroll
@@ -890,6 +949,21 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs F) {
   }
 }
 
+template <int D, int N, class PDE, int A, typename TT, typename GT>
+__global__ void __launch_bounds__(kBlock) k_face(const FaceArgs *args, const RowTile *tiles, int64_t ntiles) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, NF = S::NF;
+  constexpr int FPB = face_per_block(D, N);
+  constexpr int NG = PDE::kConservative ? 1 : 2;
+  __shared__ double sD[NG * FPB * M * n * NF];
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const RowTile t = cload(&tiles[tile]);
+    const FaceArgs F = cload(&args[t.p]);
+    face_tile<D, N, PDE, A, TT, GT>(F, t.bx, t.yz & 0xffff, t.yz >> 16, sD);
+    __syncthreads();  // the next tile overwrites the LDS
+  }
+}
+
 // ------------------------------------------------------------ update
 
 struct UpdArgs {
@@ -899,21 +973,25 @@ struct UpdArgs {
   const double *dt;
   const void *GL[3];   // GT
   const void *GR[3];
-  double *u;
+  int64_t u_off;       // offset of the problem's u in the state buffer
+  int pidx;            // problem index: its time step is dt[pidx]
+  int cx;              // tiles of kUpdChunk*kBlock nodes per x-row
 };
 
 // u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64
 // arithmetic; face integrals stored as GT).  One thread per node, all M
-// variables; grid (x-row chunks, ny, nz).
+// variables; a tile is chunk bx of kUpdChunk*kBlock nodes of the x-row
+// (iy, iz), processed kBlock nodes at a time.
+constexpr int kUpdChunk = 4;
+
 template <int D, int N, class PDE, typename GT>
-__global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
+__device__ __forceinline__ void update_nodes(const UpdArgs &U, int t, int iy, int iz, double *ubuf,
+                                             double dt) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
-  const int t = blockIdx.x * kBlock + threadIdx.x;
   const int nx = U.g.nel[0], ny = U.g.nel[1], nz = U.g.nel[2];
   if (t >= nx * ND) return;
   const int ix = t / ND, k = t - ix * ND;
-  const int iy = blockIdx.y, iz = blockIdx.z;
   const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
   const GT *gp[D], *gm[D];
   double cp[D], cm[D];
@@ -932,15 +1010,28 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
     // the - face: conservative systems use -G of the face owned by eL
     cm[A] = PDE::kConservative ? -U.g.inv_h[A] * cload(&U.ops->L0[ka]) : U.g.inv_h[A] * cload(&U.ops->L0[ka]);
   }
-  const double dt = *U.dt;
   const int64_t base = e * (M * ND) + k;
+  double *u = ubuf + U.u_off;
 #pragma unroll
   for (int v = 0; v < M; v++) {
     double acc = 0.0;
 #pragma unroll
     for (int A = 0; A < D; A++) acc += cp[A] * (double)gp[A][v * NF] + cm[A] * (double)gm[A][v * NF];
     const double us = U.ustar[base + v * ND];
-    U.u[base + v * ND] = dt == 0.0 ? us : us - dt * acc;
+    u[base + v * ND] = dt == 0.0 ? us : us - dt * acc;
+  }
+}
+
+template <int D, int N, class PDE, typename GT>
+__global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const RowTile *tiles, int64_t ntiles,
+                                                   double *u, const double *dt) {
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const RowTile t = cload(&tiles[tile]);
+    const UpdArgs U = cload(&args[t.p]);
+    const double d = cload(&dt[t.pidx]);
+#pragma unroll
+    for (int c = 0; c < kUpdChunk; c++)
+      update_nodes<D, N, PDE, GT>(U, (t.bx * kUpdChunk + c) * kBlock + threadIdx.x, t.yz & 0xffff, t.yz >> 16, u, d);
   }
 }
 
@@ -949,34 +1040,29 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs U) {
 struct CflArgs {
   Geom g;
   double h[3];
-  const double *u;
+  int64_t u_off;                  // offset of the problem's u in the state buffer
   const double *mat;
-  unsigned long long *smax_bits;  // max over elements of sum_A lambda_A/h_A (double bits)
-  int *err;
+  int pidx;                       // problem index: smax[pidx] collects its maximum
 };
 
 // Per-element wave speed S_e = sum_A (max_k |lambda_A(u_k)|) / h_A and its
-// maximum over the mesh.  Grid (1, ny, nz): each workgroup walks one x-row
-// of elements, one wavefront per element at a time, and issues a single
-// atomicMax on the bit pattern (positive doubles order like their bits, so
-// the result does not depend on the order).
+// maximum over the mesh.  A tile is one x-row of elements (tile = iy + ny iz):
+// the workgroup walks it one wavefront per element at a time and issues a
+// single atomicMax on the bit pattern of the row maximum (positive doubles
+// order like their bits, so the result does not depend on the order).
 template <int D, int N, class PDE>
-__global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
+__device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const double *u,
+                                        unsigned long long *smax_bits, int *err, double *red, int *bad_any) {
   using S = Shape<D, N>;
   constexpr int M = PDE::M, ND = S::ND;
-  __shared__ double red[kBlock / 64];
-  __shared__ int bad_any;
-  if (threadIdx.x == 0) bad_any = 0;
-  __syncthreads();
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
-  const int nx = C.g.nel[0], ny = C.g.nel[1];
-  const int64_t row = (int64_t)nx * (blockIdx.y + (int64_t)ny * blockIdx.z);
+  const int nx = C.g.nel[0];
   double smax = 0.0;
   int bad = 0;
   for (int ix = wave; ix < nx; ix += kBlock / 64) {
-    const int64_t e = row + ix;
+    const int64_t e = row * nx + ix;
     double lm[3] = {0.0, 0.0, 0.0};
-    const double *ue = C.u + e * (int64_t)(M * ND);
+    const double *ue = u + C.u_off + e * (int64_t)(M * ND);
     for (int k = lane; k < ND; k += 64) {
       double q[M];
 #pragma unroll
@@ -1014,14 +1100,31 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs C) {
     }
     smax = fmax(smax, se);
   }
-  if (bad) atomicOr(&bad_any, 1);
+  if (bad) atomicOr(bad_any, 1);
   if (lane == 0) red[wave] = smax;
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int i = 1; i < kBlock / 64; i++) m = fmax(m, red[i]);
-    atomicMax(C.smax_bits, (unsigned long long)__double_as_longlong(m));
-    if (bad_any) atomicOr(C.err, 1);
+    atomicMax(smax_bits + C.pidx, (unsigned long long)__double_as_longlong(m));
+    if (*bad_any) atomicOr(err, 1);
+    *bad_any = 0;
+  }
+  __syncthreads();  // red and bad_any are reused by the next row
+}
+
+template <int D, int N, class PDE>
+__global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs *args, const Batch b, const double *u,
+                                                unsigned long long *smax_bits, int *err) {
+  __shared__ double red[kBlock / 64];
+  __shared__ int bad_any;
+  if (threadIdx.x == 0) bad_any = 0;
+  __syncthreads();
+  const int64_t total = cload(&b.start[b.np]);
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int p = tile_problem(b, tile);
+    const CflArgs C = cload(&args[p]);
+    cfl_row<D, N, PDE>(C, tile - cload(&b.start[p]), u, smax_bits, err, red, &bad_any);
   }
 }
 

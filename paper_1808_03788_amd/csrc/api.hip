@@ -31,10 +31,11 @@ struct ProbState {
   int sweeps = 0;
   int64_t u_off = 0, u_cnt = 0, q_off = 0, q_cnt = 0;
   KernelSet ks{};
-  PredVariant pv{};                 // chosen predictor variant
+  int cls = 0;                      // kernel class (batched launches)
+  PredVariant pv{};                 // chosen predictor variant (the class's)
   bool tuned = false;               // chosen by timing (else default or forced)
   double tune_ms = 0.0;             // measured time of the chosen variant on the sample
-  const void *const *face = nullptr;  // face entries for the trace type
+  std::vector<PredVariant> cand;    // predictor variants that fit this problem
   size_t trace_elt = 8;             // bytes per trace value
   OpsSweep sw{};            // sweep operators (host copy)
   OpsSweep *sw_dev = nullptr;  // device copy read by the predictor
@@ -42,7 +43,28 @@ struct ProbState {
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
   void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};  // trace type
-  const void *update = nullptr;     // update entry for the face-integral type
+};
+
+// Problems that share every kernel (dimension, degree, PDE, precision) run
+// as one batched launch per stage: per-problem argument records and tile
+// prefixes live in device memory, and persistent workgroups stride over the
+// tiles of all problems of the class.
+struct KClass {
+  std::vector<int> probs;
+  PredVariant pv{};
+  bool tuned = false;
+  double tune_ms = 0.0;
+  int D = 0;
+  const void *face[3] = {nullptr, nullptr, nullptr};
+  const void *update = nullptr, *cfl = nullptr;
+  PredArgs *pargs = nullptr;               // device [np]
+  FaceArgs *fargs[3] = {nullptr, nullptr, nullptr};
+  UpdArgs *uargs = nullptr;
+  CflArgs *cargs = nullptr;
+  int64_t *pstart = nullptr, *cstart = nullptr;  // device [np+1]
+  RowTile *ftiles = nullptr, *utiles = nullptr;   // device [ftot], [utot]
+  int64_t ptot = 0, ftot = 0, utot = 0, ctot = 0;  // tiles
+  int pgrid = 0, fgrid[3] = {0, 0, 0}, ugrid = 0, cgrid = 0;  // persistent grid sizes
 };
 
 }  // namespace
@@ -50,8 +72,18 @@ struct ProbState {
 struct ader_ctx {
   hipStream_t stream = nullptr;
   int device = 0;
+  hipStream_t cur = nullptr;   // stream the launches go to (the capture stream while capturing)
+  hipStream_t gstream = nullptr;  // graph replays (created on first use)
+  hipGraphExec_t gexec = nullptr;
+  double *g_u = nullptr;
+  int g_steps = 0;
+  hipEvent_t g_in = nullptr, g_out = nullptr;
+  int ncu = 256;
   std::vector<ProbState> P;
+  std::vector<KClass> K;
   double *dt = nullptr, *t = nullptr, *tnext = nullptr;  // device [nprob]
+  double *coef = nullptr, *tend = nullptr;               // device [nprob]
+  std::vector<double> tend_host;                         // values held by tend
   unsigned long long *smax = nullptr;                      // device [nprob]
   int *err = nullptr;                                      // device [1]
   double *partial = nullptr, *sums = nullptr;              // totals scratch
@@ -126,27 +158,32 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
   return ADER_OK;
 }
 
-__global__ void k_finalize(unsigned long long *smax, int *err, double coef, double t_end,
-                           const double *t, double *dt, double *tnext) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double S = __longlong_as_double((long long)*smax);
-  *smax = 0ull;
+// dt of every problem from its mesh maximum S: dt = coef / S, clipped so
+// that the last step lands on t_end (when clip is set); resets the maximum.
+__global__ void k_finalize(unsigned long long *smax, int *err, const double *coef, const double *tend,
+                           int clip, const double *t, double *dt, double *tnext, int np) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i >= np) return;
+  const double S = __longlong_as_double((long long)smax[i]);
+  smax[i] = 0ull;
   double d;
   if (!(S > 0.0) || isinf(S)) {
     atomicOr(err, 1);
     d = 0.0;
   } else {
-    d = coef / S;
+    d = coef[i] / S;
   }
   if (*err) d = 0.0;
-  const double rem = t_end - *t;
-  double tn = *t + d;
-  if (rem <= d) {  // the last step lands exactly on t_end
-    d = rem > 0.0 ? rem : 0.0;
-    tn = rem > 0.0 ? t_end : *t;
+  double tn = t[i] + d;
+  if (clip) {
+    const double rem = tend[i] - t[i];
+    if (rem <= d) {  // the last step lands exactly on t_end
+      d = rem > 0.0 ? rem : 0.0;
+      tn = rem > 0.0 ? tend[i] : t[i];
+    }
   }
-  *dt = d;
-  *tnext = tn;
+  dt[i] = d;
+  tnext[i] = tn;
 }
 
 __global__ void k_commit(double *t, const double *tnext, int np) {
@@ -195,13 +232,25 @@ __global__ void k_totals_final(const double *partial, int nblk, int m, double *o
 
 int64_t blocks_for(int64_t work) { return (work + kBlock - 1) / kBlock; }
 
-ader_status launch(ader_ctx *c, const void *fn, int64_t grid, size_t shmem, void *arg,
-                   int threads = kBlock, int gy = 1, int gz = 1) {
-  if (grid <= 0) return ADER_OK;
-  if (grid > 0x7fffffff || gy > 65535 || gz > 65535) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
-  void *args[] = {arg};
-  HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid, gy, gz), dim3(threads), args, shmem, c->stream));
+// One batched launch: `grid` persistent workgroups over `tiles` tiles.
+ader_status launch(ader_ctx *c, const void *fn, int64_t tiles, int grid, int threads, size_t shmem,
+                   void **args) {
+  if (tiles <= 0) return ADER_OK;
+  if (grid < 1) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
+  HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(threads), args, shmem, c->cur));
   return ADER_OK;
+}
+
+// Persistent grid: as many workgroups as the device holds at once (at
+// least one), never more than there are tiles.
+int persistent_grid(ader_ctx *c, const void *fn, int threads, size_t shmem, int64_t tiles) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, shmem) != hipSuccess || nb < 1) {
+    (void)hipGetLastError();
+    nb = 1;
+  }
+  const int64_t cap = (int64_t)nb * c->ncu;
+  return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
 // Uniform state u[e][v][k] = val[v] (used to time predictor variants).
@@ -217,27 +266,39 @@ __global__ void k_fill_state(double *u, int64_t count, int m, int nd, double v0,
 std::mutex g_tune_mu;
 std::map<std::string, std::string> g_tune_cache;  // configuration -> variant name
 
-PredArgs pred_args(ProbState &s, const double *u, const double *dt, double *qhat) {
+PredArgs pred_args(const ProbState &s, int p) {
   PredArgs a{};
   a.sw = s.sw_dev;
   a.ops = s.ops_dev;
   a.g = s.g;
-  a.u = u;
-  a.dt = dt;
+  a.u_off = s.u_off;
+  a.q_off = s.q_off;
+  a.pidx = p;
   a.mat = s.mat;
   a.ustar = s.ustar;
   for (int ax = 0; ax < 3; ax++)
     for (int sd = 0; sd < 2; sd++) a.trace[ax][sd] = s.trace[ax][sd];
-  a.qhat = qhat;
   a.acc_glob = s.acc;
   a.sweeps = s.sweeps;
   return a;
 }
 
-// Time every candidate predictor variant on a uniform state of up to 32768
-// elements (the kernels have no data-dependent branches) and keep the
-// fastest.  Results are cached per configuration for the process.
-ader_status tune_predictor(ader_ctx *c, ProbState &s, int p, const std::vector<PredVariant> &cand) {
+ader_status upload(ader_ctx *c, void **dst, const void *src, size_t bytes) {
+  ader_status st = dalloc(c, dst, bytes);
+  if (st) return st;
+  HIP_OR_FAIL(c, hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return ADER_OK;
+}
+
+// Time every candidate predictor variant of a class on a uniform state of
+// up to 32768 elements of its largest problem (the kernels have no
+// data-dependent branches) and keep the fastest.  Results are cached per
+// configuration for the process.
+ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &cand) {
+  int pl = k.probs[0];
+  for (int p : k.probs)
+    if (c->P[p].E > c->P[pl].E) pl = p;
+  ProbState &s = c->P[pl];
   const int64_t Et = s.E < 32768 ? s.E : 32768;
   const std::string key = std::to_string(s.D) + "/" + std::to_string(s.N) + "/" +
                           std::to_string(s.desc.pde) + "/" + std::to_string(s.desc.prec) + "/" +
@@ -248,8 +309,8 @@ ader_status tune_predictor(ader_ctx *c, ProbState &s, int p, const std::vector<P
     if (it != g_tune_cache.end())
       for (const PredVariant &v : cand)
         if (it->second == v.name) {
-          s.pv = v;
-          s.tuned = true;
+          k.pv = v;
+          k.tuned = true;
           return ADER_OK;
         }
   }
@@ -259,28 +320,42 @@ ader_status tune_predictor(ader_ctx *c, ProbState &s, int p, const std::vector<P
     (void)hipGetLastError();
     return ADER_OK;  // no room to tune: keep the default
   }
+  PredArgs a = pred_args(s, pl);
+  a.u_off = 0;
+  const int64_t start[2] = {0, Et};
+  PredArgs *a_dev = nullptr;
+  int64_t *st_dev = nullptr;
+  ader_status st;
+  if ((st = upload(c, (void **)&a_dev, &a, sizeof(a))) || (st = upload(c, (void **)&st_dev, start, sizeof(start)))) {
+    (void)hipFree(ut);
+    return st;
+  }
   const double ie = 1.0 / (s.desc.gamma - 1.0);  // Euler: rho = 1, v = 0, p = 1
   const unsigned nb = (unsigned)((cnt + 255) / 256);
   if (s.desc.pde == ADER_EULER)
-    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->stream, ut, cnt, s.m, s.nd, 1.0, 0.0, 0.0,
+    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->cur, ut, cnt, s.m, s.nd, 1.0, 0.0, 0.0,
                        s.D == 2 ? ie : 0.0, s.D == 3 ? ie : 0.0);
   else
-    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->stream, ut, cnt, s.m, s.nd, 0.0, 0.0, 0.0,
+    hipLaunchKernelGGL(k_fill_state, dim3(nb), dim3(256), 0, c->cur, ut, cnt, s.m, s.nd, 0.0, 0.0, 0.0,
                        1.0, 1.0);
   const double dt_tune = 1e-6;
-  HIP_OR_FAIL(c, hipMemcpyAsync(c->dt + p, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->stream));
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->dt + pl, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->cur));
   hipEvent_t e0, e1;
   HIP_OR_FAIL(c, hipEventCreate(&e0));
   HIP_OR_FAIL(c, hipEventCreate(&e1));
-  PredArgs a = pred_args(s, ut, c->dt + p, nullptr);
+  Batch b{st_dev, 1};
+  const double *dtp = c->dt;
+  double *qn = nullptr;
+  void *args[] = {&a_dev, &b, &ut, &dtp, &qn};
   double best = 1e30;
-  PredVariant bestv = s.pv;
-  ader_status st = ADER_OK;
+  PredVariant bestv = k.pv;
+  st = ADER_OK;
   for (const PredVariant &v : cand) {
-    if ((st = launch(c, v.fn, Et, v.lds, &a, v.threads))) break;  // warm-up
-    HIP_OR_FAIL(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < 3 && !st; r++) st = launch(c, v.fn, Et, v.lds, &a, v.threads);
-    HIP_OR_FAIL(c, hipEventRecord(e1, c->stream));
+    const int grid = (int)Et;  // one element per workgroup
+    if ((st = launch(c, v.fn, Et, grid, v.threads, v.lds, args))) break;  // warm-up
+    HIP_OR_FAIL(c, hipEventRecord(e0, c->cur));
+    for (int r = 0; r < 3 && !st; r++) st = launch(c, v.fn, Et, grid, v.threads, v.lds, args);
+    HIP_OR_FAIL(c, hipEventRecord(e1, c->cur));
     HIP_OR_FAIL(c, hipEventSynchronize(e1));
     float ms = 0.f;
     HIP_OR_FAIL(c, hipEventElapsedTime(&ms, e0, e1));
@@ -292,54 +367,40 @@ ader_status tune_predictor(ader_ctx *c, ProbState &s, int p, const std::vector<P
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->cur));
   (void)hipFree(ut);
   if (st) return st;
   const double zero = 0.0;
-  HIP_OR_FAIL(c, hipMemcpy(c->dt + p, &zero, sizeof(double), hipMemcpyHostToDevice));
-  s.pv = bestv;
-  s.tuned = true;
-  s.tune_ms = best;
+  HIP_OR_FAIL(c, hipMemcpy(c->dt + pl, &zero, sizeof(double), hipMemcpyHostToDevice));
+  k.pv = bestv;
+  k.tuned = true;
+  k.tune_ms = best;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = bestv.name;
   return ADER_OK;
 }
 
-ader_status run_cfl(ader_ctx *c, const double *u, const double *t_end_host) {
-  for (size_t p = 0; p < c->P.size(); p++) {
+// Argument records, tile prefixes and persistent grids of a class.
+ader_status build_class(ader_ctx *c, KClass &k) {
+  const int np = (int)k.probs.size();
+  std::vector<PredArgs> pa(np);
+  std::vector<FaceArgs> fa[3];
+  std::vector<UpdArgs> ua(np);
+  std::vector<CflArgs> ca(np);
+  std::vector<int64_t> ps(np + 1, 0), cs(np + 1, 0);
+  std::vector<RowTile> ft, ut;
+  const int fpb = face_per_block(k.D, c->P[k.probs[0]].N);
+  for (int a = 0; a < 3; a++) fa[a].resize(np);
+  for (int i = 0; i < np; i++) {
+    const int p = k.probs[i];
     ProbState &s = c->P[p];
-    CflArgs a{};
-    a.g = s.g;
-    for (int i = 0; i < 3; i++) a.h[i] = s.h[i];
-    a.u = u + s.u_off;
-    a.mat = s.mat;
-    a.smax_bits = c->smax + p;
-    a.err = c->err;
-    ader_status st = launch(c, s.ks.cfl, 1, 0, &a, kBlock, s.g.nel[1], s.g.nel[2]);
-    if (st) return st;
-    const double te = t_end_host ? t_end_host[p] : INFINITY;
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(1), 0, c->stream, c->smax + p, c->err, s.coef, te,
-                       c->t + p, c->dt + p, c->tnext + p);
-    HIP_OR_FAIL(c, hipGetLastError());
-  }
-  return ADER_OK;
-}
-
-ader_status run_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat) {
-  for (size_t p = 0; p < c->P.size(); p++) {
-    ProbState &s = c->P[p];
-    PredArgs a = pred_args(s, u + s.u_off, (dt_dev ? dt_dev : c->dt) + p, qhat ? qhat + s.q_off : nullptr);
-    ader_status st = launch(c, s.pv.fn, s.E, s.pv.lds, &a, s.pv.threads);
-    if (st) return st;
-  }
-  return ADER_OK;
-}
-
-ader_status run_faces(ader_ctx *c) {
-  for (size_t p = 0; p < c->P.size(); p++) {
-    ProbState &s = c->P[p];
+    s.pv = k.pv;
+    s.tuned = k.tuned;
+    s.tune_ms = k.tune_ms;
+    pa[i] = pred_args(s, p);
+    const int nx = s.g.nel[0], rows = s.g.nel[1] * s.g.nel[2];
     for (int ax = 0; ax < s.D; ax++) {
-      FaceArgs f{};
+      FaceArgs &f = fa[ax][i];
       f.ops = s.ops_dev;
       f.g = s.g;
       f.trace0 = s.trace[ax][0];
@@ -347,9 +408,92 @@ ader_status run_faces(ader_ctx *c) {
       f.mat = s.mat;
       f.GL = s.GL[ax];
       f.GR = s.GR[ax];
-      const int fpb = face_per_block(s.D, s.N);
-      ader_status st = launch(c, s.face[ax], (s.g.nel[0] + fpb - 1) / fpb, 0, &f, kBlock, s.g.nel[1],
-                              s.g.nel[2]);
+      f.cx = (nx + fpb - 1) / fpb;
+    }
+    UpdArgs &u = ua[i];
+    u.ops = s.ops_dev;
+    u.g = s.g;
+    u.ustar = s.ustar;
+    for (int ax = 0; ax < 3; ax++) {
+      u.GL[ax] = s.GL[ax];
+      u.GR[ax] = s.GR[ax];
+    }
+    u.u_off = s.u_off;
+    u.pidx = p;
+    u.cx = (int)((blocks_for((int64_t)nx * s.nd) + kUpdChunk - 1) / kUpdChunk);
+    CflArgs &cf = ca[i];
+    cf.g = s.g;
+    for (int ax = 0; ax < 3; ax++) cf.h[ax] = s.h[ax];
+    cf.u_off = s.u_off;
+    cf.mat = s.mat;
+    cf.pidx = p;
+    ps[i + 1] = ps[i] + s.E;
+    cs[i + 1] = cs[i] + rows;
+    for (int r = 0; r < rows; r++) {
+      const int iy = r % s.g.nel[1], iz = r / s.g.nel[1];
+      for (int bx = 0; bx < fa[0][i].cx; bx++) ft.push_back(RowTile{i, p, bx, iy | iz << 16});
+      for (int bx = 0; bx < u.cx; bx++) ut.push_back(RowTile{i, p, bx, iy | iz << 16});
+    }
+  }
+  ader_status st;
+  const size_t b64 = (np + 1) * sizeof(int64_t);
+  if ((st = upload(c, (void **)&k.pargs, pa.data(), np * sizeof(PredArgs))) ||
+      (st = upload(c, (void **)&k.uargs, ua.data(), np * sizeof(UpdArgs))) ||
+      (st = upload(c, (void **)&k.cargs, ca.data(), np * sizeof(CflArgs))) ||
+      (st = upload(c, (void **)&k.pstart, ps.data(), b64)) || (st = upload(c, (void **)&k.cstart, cs.data(), b64)) ||
+      (st = upload(c, (void **)&k.ftiles, ft.data(), ft.size() * sizeof(RowTile))) ||
+      (st = upload(c, (void **)&k.utiles, ut.data(), ut.size() * sizeof(RowTile))))
+    return st;
+  for (int ax = 0; ax < k.D; ax++)
+    if ((st = upload(c, (void **)&k.fargs[ax], fa[ax].data(), np * sizeof(FaceArgs)))) return st;
+  k.ptot = ps[np];
+  k.ftot = (int64_t)ft.size();
+  k.utot = (int64_t)ut.size();
+  k.ctot = cs[np];
+  if (k.ptot > 0x7fffffff) return fail(c, ADER_ERR_UNSUPPORTED, "more than 2^31-1 elements in one kernel class");
+  k.pgrid = (int)k.ptot;  // the predictor takes one element per workgroup
+  // face, update and time-step kernels: one tile per workgroup as well (the
+  // grid-stride loops then run once); these stages are bound by HBM and
+  // gain from every workgroup the device can hold
+  if (k.ftot > 0x7fffffff || k.utot > 0x7fffffff) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
+  for (int ax = 0; ax < k.D; ax++) k.fgrid[ax] = (int)k.ftot;
+  k.ugrid = (int)k.utot;
+  k.cgrid = (int)k.ctot;
+  return ADER_OK;
+}
+
+// Per-problem maxima of the wave speed, then every problem's dt (clipped
+// to the t_end values held by c->tend when clip is set).
+ader_status run_cfl(ader_ctx *c, const double *u, int clip) {
+  for (KClass &k : c->K) {
+    Batch b{k.cstart, (int)k.probs.size()};
+    void *args[] = {&k.cargs, &b, &u, &c->smax, &c->err};
+    ader_status st = launch(c, k.cfl, k.ctot, k.cgrid, kBlock, 0, args);
+    if (st) return st;
+  }
+  const int np = (int)c->P.size();
+  hipLaunchKernelGGL(k_finalize, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->smax, c->err, c->coef,
+                     c->tend, clip, c->t, c->dt, c->tnext, np);
+  HIP_OR_FAIL(c, hipGetLastError());
+  return ADER_OK;
+}
+
+ader_status run_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat) {
+  const double *dt = dt_dev ? dt_dev : c->dt;
+  for (KClass &k : c->K) {
+    Batch b{k.pstart, (int)k.probs.size()};
+    void *args[] = {&k.pargs, &b, &u, &dt, &qhat};
+    ader_status st = launch(c, k.pv.fn, k.ptot, k.pgrid, k.pv.threads, k.pv.lds, args);
+    if (st) return st;
+  }
+  return ADER_OK;
+}
+
+ader_status run_faces(ader_ctx *c) {
+  for (KClass &k : c->K) {
+    for (int ax = 0; ax < k.D; ax++) {
+      void *args[] = {&k.fargs[ax], &k.ftiles, &k.ftot};
+      ader_status st = launch(c, k.face[ax], k.ftot, k.fgrid[ax], kBlock, 0, args);
       if (st) return st;
     }
   }
@@ -357,20 +501,10 @@ ader_status run_faces(ader_ctx *c) {
 }
 
 ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
-  for (size_t p = 0; p < c->P.size(); p++) {
-    ProbState &s = c->P[p];
-    UpdArgs a{};
-    a.ops = s.ops_dev;
-    a.g = s.g;
-    a.ustar = s.ustar;
-    a.dt = (dt_dev ? dt_dev : c->dt) + p;
-    for (int ax = 0; ax < 3; ax++) {
-      a.GL[ax] = s.GL[ax];
-      a.GR[ax] = s.GR[ax];
-    }
-    a.u = u + s.u_off;
-    ader_status st = launch(c, s.update, blocks_for((int64_t)s.g.nel[0] * s.nd), 0, &a, kBlock,
-                            s.g.nel[1], s.g.nel[2]);
+  const double *dt = dt_dev ? dt_dev : c->dt;
+  for (KClass &k : c->K) {
+    void *args[] = {&k.uargs, &k.utiles, &k.utot, &u, &dt};
+    ader_status st = launch(c, k.update, k.utot, k.ugrid, kBlock, 0, args);
     if (st) return st;
   }
   return ADER_OK;
@@ -391,7 +525,7 @@ ader_status mark(ader_ctx *c) {
     HIP_OR_FAIL(c, hipEventCreate(&ev));
   }
   c->ev_used.push_back(ev);
-  HIP_OR_FAIL(c, hipEventRecord(ev, c->stream));
+  HIP_OR_FAIL(c, hipEventRecord(ev, c->cur));
   return ADER_OK;
 }
 
@@ -405,6 +539,39 @@ ader_status check_flag(ader_ctx *c) {
     HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
     return fail(c, ADER_ERR_NONFINITE, "non-finite or non-physical state (NaN/Inf, rho <= 0 or p <= 0)");
   }
+  return ADER_OK;
+}
+
+// Make the device t_end values equal to t_end_host (a synchronous copy,
+// only when they change).
+ader_status set_tend(ader_ctx *c, const double *t_end_host) {
+  const size_t np = c->P.size();
+  bool same = true;
+  for (size_t i = 0; i < np && same; i++) same = c->tend_host[i] == t_end_host[i];
+  if (same) return ADER_OK;
+  if (c->gexec) {  // a captured replay may still read the old values
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->gstream));
+  }
+  c->tend_host.assign(t_end_host, t_end_host + np);
+  HIP_OR_FAIL(c, hipMemcpyAsync(c->tend, c->tend_host.data(), np * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+// The launches of one step on c->cur: dt, predictor, faces, update, commit
+// of the new time.  Profiling events are recorded only outside captures.
+ader_status step_launches(ader_ctx *c, double *u, bool marks) {
+  ader_status st;
+  const bool m = marks && c->profile;
+  if ((m && (st = mark(c))) || (st = run_cfl(c, u, 1))) return st;
+  if ((m && (st = mark(c))) || (st = run_predictor(c, u, nullptr, nullptr))) return st;
+  if ((m && (st = mark(c))) || (st = run_faces(c))) return st;
+  if ((m && (st = mark(c))) || (st = run_update(c, u, nullptr))) return st;
+  if (m && (st = mark(c))) return st;
+  const int np = (int)c->P.size();
+  hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->t, c->tnext, np);
+  HIP_OR_FAIL(c, hipGetLastError());
   return ADER_OK;
 }
 
@@ -447,6 +614,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   }
   ader_ctx *c = new ader_ctx();
   c->stream = (hipStream_t)hip_stream;
+  c->cur = c->stream;
   ader_status st = ADER_OK;
   auto bail = [&](ader_status s) {
     g_create_msg = c->msg;  // readable through ader_last_error(NULL)
@@ -460,8 +628,14 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     c->msg = "no HIP device";
     return bail(ADER_ERR_DEVICE);
   }
+  {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
+      c->ncu = ncu;
+    else
+      (void)hipGetLastError();
+  }
   c->P.resize(nprob);
-  std::vector<std::vector<PredVariant>> tune_list;  // per problem: candidates to time
   int64_t uoff = 0, qoff = 0, moff = 0;
   for (int i = 0; i < nprob; i++) {
     const ader_problem &d = probs[i];
@@ -517,8 +691,6 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     }
     const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
     s.trace_elt = d.prec == ADER_FP64 ? sizeof(double) : sizeof(float);
-    s.face = d.prec == ADER_FP64 ? s.ks.face64 : s.ks.face32;
-    s.update = d.prec == ADER_FP64 ? s.ks.update64 : s.ks.update32;
     // candidate predictor variants: this precision, within the LDS budget;
     // for FP64 the HBM-accumulator variant only when no LDS variant fits
     std::vector<PredVariant> cand;
@@ -546,17 +718,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       return bail(ADER_ERR_UNSUPPORTED);
     }
     s.pv = cand[0];
-    const char *force = getenv("ADER_VARIANT");
-    bool forced = false;
-    if (force && *force)
-      for (const PredVariant &pv : cand)
-        if (strcmp(pv.name, force) == 0) {
-          s.pv = pv;
-          forced = true;
-        }
-    const char *tune_env = getenv("ADER_AUTOTUNE");
-    const bool tune = !forced && cand.size() > 1 && !(tune_env && strcmp(tune_env, "0") == 0);
-    tune_list.push_back(tune ? cand : std::vector<PredVariant>());
+    s.cand = cand;
     // device buffers
     if ((st = dalloc(c, (void **)&s.ops_dev, sizeof(Ops)))) return bail(st);
     if ((st = dalloc(c, (void **)&s.sw_dev, sizeof(OpsSweep)))) return bail(st);
@@ -575,6 +737,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       if ((st = dalloc(c, (void **)&s.GL[a], gb))) return bail(st);
       if (d.pde == ADER_ELASTIC && (st = dalloc(c, (void **)&s.GR[a], gb))) return bail(st);
     }
+    // every candidate shares acc_lds (the first pass that finds any fixes it)
     if (!s.pv.acc_lds && (st = dalloc(c, (void **)&s.acc, (size_t)s.E * acc_bytes))) return bail(st);
     if (d.pde == ADER_ELASTIC) {
       if ((st = dalloc(c, (void **)&s.mat, (size_t)s.E * 3 * sizeof(double)))) return bail(st);
@@ -592,6 +755,14 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   if ((st = dalloc(c, (void **)&c->t, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->tnext, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->smax, nprob * sizeof(unsigned long long)))) return bail(st);
+  {
+    std::vector<double> coef(nprob);
+    for (int i = 0; i < nprob; i++) coef[i] = c->P[i].coef;
+    c->tend_host.assign(nprob, INFINITY);
+    if ((st = upload(c, (void **)&c->coef, coef.data(), nprob * sizeof(double))) ||
+        (st = upload(c, (void **)&c->tend, c->tend_host.data(), nprob * sizeof(double))))
+      return bail(st);
+  }
   if ((st = dalloc(c, (void **)&c->err, sizeof(int)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->partial, (size_t)kTotBlocks * 9 * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->sums, (size_t)c->total_m * sizeof(double)))) return bail(st);
@@ -603,8 +774,42 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     c->msg = "initialisation failed";
     return bail(ADER_ERR_DEVICE);
   }
-  for (int i = 0; i < nprob; i++)
-    if (!tune_list[i].empty() && (st = tune_predictor(c, c->P[i], i, tune_list[i]))) return bail(st);
+  // kernel classes: problems with the same kernels share every launch
+  const char *force = getenv("ADER_VARIANT");
+  const char *tune_env = getenv("ADER_AUTOTUNE");
+  for (int i = 0; i < nprob; i++) {
+    ProbState &s = c->P[i];
+    int k = 0;
+    for (; k < (int)c->K.size(); k++) {
+      const ProbState &r = c->P[c->K[k].probs[0]];
+      if (r.D == s.D && r.N == s.N && r.desc.pde == s.desc.pde && r.desc.prec == s.desc.prec) break;
+    }
+    if (k == (int)c->K.size()) {
+      KClass kc;
+      kc.D = s.D;
+      kc.pv = s.cand[0];
+      const bool f64 = s.desc.prec == ADER_FP64;
+      for (int ax = 0; ax < 3; ax++) kc.face[ax] = f64 ? s.ks.face64[ax] : s.ks.face32[ax];
+      kc.update = f64 ? s.ks.update64 : s.ks.update32;
+      kc.cfl = s.ks.cfl;
+      c->K.push_back(kc);
+    }
+    s.cls = k;
+    c->K[k].probs.push_back(i);
+  }
+  for (KClass &k : c->K) {
+    const std::vector<PredVariant> &cand = c->P[k.probs[0]].cand;
+    bool forced = false;
+    if (force && *force)
+      for (const PredVariant &pv : cand)
+        if (strcmp(pv.name, force) == 0) {
+          k.pv = pv;
+          forced = true;
+        }
+    const bool tune = !forced && cand.size() > 1 && !(tune_env && strcmp(tune_env, "0") == 0);
+    if (tune && (st = tune_class(c, k, cand))) return bail(st);
+    if ((st = build_class(c, k))) return bail(st);
+  }
   *out = c;
   return ADER_OK;
 }
@@ -636,7 +841,12 @@ ader_status ader_stage_times(ader_ctx *c, double *ms_host, int64_t *launches_hos
 
 ader_status ader_destroy(ader_ctx *c) {
   if (!c) return ADER_OK;
-  if (!c->allocs.empty() || !c->ev_used.empty() || !c->ev_pool.empty()) (void)hipDeviceSynchronize();
+  if (!c->allocs.empty() || !c->ev_used.empty() || !c->ev_pool.empty() || c->gstream)
+    (void)hipDeviceSynchronize();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->g_in) (void)hipEventDestroy(c->g_in);
+  if (c->g_out) (void)hipEventDestroy(c->g_out);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
   for (hipEvent_t e : c->ev_used) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   for (void *p : c->allocs) (void)hipFree(p);
@@ -667,7 +877,7 @@ ader_status ader_state_size(const ader_ctx *c, int64_t *count) {
 ader_status ader_cfl_dt(ader_ctx *c, const double *u, double *dt_host) {
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
-  ader_status st = run_cfl(c, u, nullptr);
+  ader_status st = run_cfl(c, u, 0);
   if (st || !dt_host) return st;
   HIP_OR_FAIL(c, hipMemcpyAsync(dt_host, c->dt, c->P.size() * sizeof(double), hipMemcpyDeviceToHost,
                                 c->stream));
@@ -689,15 +899,53 @@ ader_status ader_corrector(ader_ctx *c, double *u, const double *dt_dev) {
 ader_status ader_step(ader_ctx *c, double *u, const double *t_end_host) {
   if (!c) return ADER_ERR_INVALID;
   if (!u || !t_end_host) return fail(c, ADER_ERR_INVALID, "u and t_end must not be NULL");
-  ader_status st;
-  if ((st = mark(c)) || (st = run_cfl(c, u, t_end_host))) return st;
-  if ((st = mark(c)) || (st = run_predictor(c, u, nullptr, nullptr))) return st;
-  if ((st = mark(c)) || (st = run_faces(c))) return st;
-  if ((st = mark(c)) || (st = run_update(c, u, nullptr))) return st;
-  if ((st = mark(c))) return st;
-  const int np = (int)c->P.size();
-  hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->stream, c->t, c->tnext, np);
-  HIP_OR_FAIL(c, hipGetLastError());
+  ader_status st = set_tend(c, t_end_host);
+  return st ? st : step_launches(c, u, true);
+}
+
+ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t nsteps) {
+  if (!c) return ADER_ERR_INVALID;
+  if (!u || !t_end_host) return fail(c, ADER_ERR_INVALID, "u and t_end must not be NULL");
+  if (nsteps < 1) return fail(c, ADER_ERR_INVALID, "nsteps must be >= 1");
+  ader_status st = set_tend(c, t_end_host);
+  if (st) return st;
+  if (!c->gstream) {
+    HIP_OR_FAIL(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+    HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->g_in, hipEventDisableTiming));
+    HIP_OR_FAIL(c, hipEventCreateWithFlags(&c->g_out, hipEventDisableTiming));
+  }
+  if (!c->gexec || c->g_u != u || c->g_steps != nsteps) {
+    if (c->gexec) {
+      HIP_OR_FAIL(c, hipStreamSynchronize(c->gstream));
+      (void)hipGraphExecDestroy(c->gexec);
+      c->gexec = nullptr;
+    }
+    HIP_OR_FAIL(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+    c->cur = c->gstream;
+    for (int i = 0; i < nsteps && !st; i++) st = step_launches(c, u, false);
+    c->cur = c->stream;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->gstream, &g);
+    if (st) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (ec != hipSuccess) return fail(c, ADER_ERR_DEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+    const hipError_t ei = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) {
+      c->gexec = nullptr;
+      return fail(c, ADER_ERR_DEVICE, std::string("graph instantiation: ") + hipGetErrorString(ei));
+    }
+    c->g_u = u;
+    c->g_steps = nsteps;
+  }
+  // order the replay after earlier work on the context stream, and later work after it
+  HIP_OR_FAIL(c, hipEventRecord(c->g_in, c->stream));
+  HIP_OR_FAIL(c, hipStreamWaitEvent(c->gstream, c->g_in, 0));
+  HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, c->gstream));
+  HIP_OR_FAIL(c, hipEventRecord(c->g_out, c->gstream));
+  HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->g_out, 0));
   return ADER_OK;
 }
 
