@@ -1,13 +1,23 @@
 """Benchmark of the ADER-DG step on one MI355X.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--prec fp64|fp32|bf16]
+                    [--workload density|elastic|batched|fourier]
 
-Workload: 3-D compressible Euler (gamma = 1.4) on the periodic unit cube,
-64^3 elements, degree N = 4 (125 nodes per element, 32.8 M spatial DOFs),
-density wave rho = 1 + 0.2 sin(2 pi (x+y+z)) with u = (1,1,1), p = 1 plus
-seeded 1e-3 uniform noise on rho, CFL 0.9.  A step is one full ADER-DG step
-(time-step reduction, predictor, face integrals, update) on inputs resident
-in HBM.  Prints one JSON line.
+Default workload (density): 3-D compressible Euler (gamma = 1.4) on the
+periodic unit cube, 64^3 elements, degree N = 4 (125 nodes per element,
+32.8 M spatial DOFs), density wave rho = 1 + 0.2 sin(2 pi (x+y+z)) with
+u = (1,1,1), p = 1 plus seeded 1e-3 uniform noise on rho, CFL 0.9.  A step
+is one full ADER-DG step (time-step reduction, predictor, face integrals,
+update) on inputs resident in HBM.  Every run times the FP64 path and the
+chosen precision on the same inputs.  Other workloads:
+  elastic  3-D linear elasticity, 48^3 elements, N = 5, four seeded layers,
+           Gaussian stress pulse of width 0.05;
+  batched  256 seeded 3-D Euler density waves, meshes 8^3..32^3, N in 2..6,
+           each problem advancing `--graph-steps` of its own steps per
+           captured-graph replay (a timed step is one replay);
+  fourier  3-D Euler, 128^3 elements, N = 3, 8 seeded Fourier modes of
+           amplitude 0.05 (the bandwidth-bound configuration).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,25 +39,36 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2
         "fp64_mfma": 78.6, "hbm": 8000.0}
 
 
-def predictor_flops(d: int, N: int, m: int, sweeps: int, cF: int = 31) -> float:
-    """Algorithmic (sum-factorised) flops of the predictor for one element of
-    3-D Euler, counting a multiply-add as 2 flops and a division as 1:
+def predictor_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False, cF: int = 31,
+                    cB: int = 15) -> float:
+    """Algorithmic (sum-factorised) flops of the predictor for one element,
+    counting a multiply-add as 2 flops and a division as 1.
+    Euler (m = d+2):
       per sweep: cF flux flops per space-time node (the primitive variables
         once, 7 flops per axis), d axis contractions and 1 time contraction
         at 2n flops per output, and 2 flops per output for u + dt * (...);
       outputs: one more flux evaluation, the time average (2 flops per
         output and axis), the volume contraction (2n per output and axis),
-        u* = u + dt V and the 2d face traces (2n per trace value)."""
+        u* = u + dt V and the 2d face traces (2n per trace value).
+    Elasticity (m = 9): the flux evaluation is replaced by cB flops per
+      space-time node and axis for B_A (Dhat q) (velocity rows 3, stress
+      rows 12); the volume term contracts the time average (2n per value)
+      and applies B_A once per spatial node and axis."""
     n = N + 1
     nst = n ** (d + 1)
     nd = n ** d
-    sweep = cF * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
-    outputs = cF * nst + 2 * m * d * nst + d * 2 * n * m * nd + 2 * m * nd + 2 * d * 2 * n * m * nd
+    if not elastic:
+        sweep = cF * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
+        outputs = cF * nst + 2 * m * d * nst + d * 2 * n * m * nd + 2 * m * nd + 2 * d * 2 * n * m * nd
+    else:
+        sweep = d * cB * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
+        outputs = 2 * n * m * nd + d * (2 * n * m * nd + cB * nd) + 2 * m * nd + 2 * d * 2 * n * m * nd
     return sweeps * sweep + outputs
 
 
 def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
-    """Algorithmic HBM bytes per element per step, per stage."""
+    """Algorithmic HBM bytes per element per step, per stage (elasticity,
+    m = 9, stores a face integral for each side of a face)."""
     n = N + 1
     nd = n ** d
     nf = nd // n
@@ -57,7 +78,7 @@ def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
     return {
         "cfl": u,
         "predictor": u + u + 2 * d * trace,  # read u, write u*, write 2d traces
-        "face": d * (2 * trace + g),          # read both traces, write G, per axis
+        "face": d * (2 * trace + (2 if m == 9 else 1) * g),  # read both traces, write G, per axis
         "update": u + 2 * d * g + u,          # read u* and the 2d face blocks, write u
     }
 
@@ -86,78 +107,160 @@ def traffic_from_profiles(prec: str):
     return rec.get(prec, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(seconds: float = 12.0) -> dict:
-    """The FP64 oracle on a bounded sample of the same workload: a periodic
-    16^3-element box with the same degree, PDE and initial-data recipe, as
-    many steps as fit in about `seconds` (at least one)."""
+def cpu_baseline(workload: str = "density", seconds: float = 12.0) -> dict:
+    """The FP64 oracle on a bounded sample of the workload (same degree,
+    PDE and initial-data recipe on a smaller mesh, or a few of the batched
+    problems), as many steps as fit in about `seconds` (at least one)."""
     import oracle
     from paper_1808_03788_amd import inputs as I
-    prob = I.density_wave_problem(nel=16, N=4)
-    u = I.density_wave(prob)
-    t, steps = 0.0, 0
+    if workload == "batched":
+        items = sorted(I.batched_problems(count=256, seed=0, prec="fp64"), key=lambda it: it[0].E * it[0].nd)[:8]
+        probs = [p for p, _ in items]
+        us = [I.density_wave(p, **kw) for p, kw in items]
+        what = "the 8 smallest of the 256 batched problems"
+    else:
+        probs, us, _ = make_workload(workload, "fp64", I, nel={"density": 16, "elastic": 12,
+                                                               "fourier": 32}[workload])
+        what = f"{probs[0].nel[0]}^3 elements of the same recipe"
+    ts = [0.0] * len(probs)
+    steps = 0
     t0 = time.perf_counter()
     while True:
-        u, t, _ = oracle.step(prob, u, t, 1e9)
+        for i, p in enumerate(probs):
+            us[i], ts[i], _ = oracle.step(p, us[i], ts[i], 1e9)
         steps += 1
         el = time.perf_counter() - t0
         if el >= seconds or steps >= 50:
             break
+    dofs = sum(p.E * p.nd for p in probs)
     return {
-        "value": prob.E * prob.nd * steps / el,
+        "value": dofs * steps / el,
         "unit": "DOF-updates/s",
         "cores": oracle.num_threads(),
         "kind": "oracle",
-        "sample": f"3-D Euler density wave, 16^3 elements, N=4, {steps} steps, "
-                  f"{el:.1f} s, plain C -O2 FP64 with OpenMP over elements",
+        "sample": f"{what}, N={probs[0].N if len(probs) == 1 else 'mixed'}, {steps} steps, {el:.1f} s, "
+                  f"plain C -O2 FP64 with OpenMP over elements",
     }
 
 
-def run_path(prob_kw, prec, steps, warmup, I, ader, torch):
-    """Time `steps` full steps of one precision mode; returns the timings,
-    stage times and the final state (device tensor)."""
-    prob = I.density_wave_problem(prec=prec, **prob_kw)
-    u0 = I.density_wave(prob)
-    ctx = ader.Context([prob])
+def note(msg):
+    """Progress on stderr (the JSON result is the only stdout line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(workload, prec, I, nel=None, degree=None, picard=0):
+    """(problems, initial states, description) of a workload."""
+    if workload == "density":
+        prob = I.density_wave_problem(nel=nel or 64, N=4 if degree is None else degree, prec=prec,
+                                      picard=picard)
+        desc = (f"3-D Euler density wave, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
+                f"CFL 0.9, 1e-3 seeded noise")
+        return [prob], [I.density_wave(prob)], desc
+    if workload == "elastic":
+        prob = I.elastic_problem(nel=nel or 48, N=5 if degree is None else degree, prec=prec, picard=picard)
+        desc = (f"3-D linear elasticity, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
+                f"4 seeded layers (rho 2000-3000, cp 3000-6000, cs = cp/sqrt 3), stress pulse width 0.05")
+        return [prob], [I.stress_pulse(prob)], desc
+    if workload == "fourier":
+        prob = I.fourier_problem(nel=nel or 128, N=3 if degree is None else degree, prec=prec, picard=picard)
+        desc = (f"3-D Euler, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, 8 seeded Fourier "
+                f"modes of amplitude 0.05 on rho = 1, p = 1")
+        return [prob], [I.fourier_modes(prob)], desc
+    if workload == "batched":
+        items = I.batched_problems(count=256, seed=0, prec=prec)
+        probs = [p for p, _ in items]
+        if picard:
+            for p in probs:
+                p.picard = picard
+        inits = [I.density_wave(p, **kw) for p, kw in items]
+        desc = ("256 seeded 3-D Euler density waves, meshes 8^3..32^3, N in 2..6, one context, "
+                "batched launches per degree, captured-graph replays")
+        return probs, inits, desc
+    raise ValueError(workload)
+
+
+def run_path(workload, prec, steps, warmup, I, ader, torch, nel=None, degree=None, picard=0,
+             graph_steps=0):
+    """Time `steps` steps (or graph replays of `graph_steps` steps each) of
+    one precision mode; returns the timings, stage times and the final state
+    (device tensor)."""
+    probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard)
+    note(f"{prec}: {len(probs)} problem(s) generated")
+    ctx = ader.Context(probs)
+    note(f"{prec}: context created ({ader.ader_describe(ctx.ctx, 0).split()[0]})")
     kernels = ader.ader_describe(ctx.ctx, 0)
-    u = ctx.upload([u0])
-    del u0
+    u = ctx.upload(inits)
+    del inits
+    big = [1e9] * len(probs)
+
+    def advance():
+        if graph_steps:
+            ctx.run(u, big, graph_steps)
+        else:
+            ctx.step(u, big)
+
     for _ in range(warmup):
-        ctx.step(u, 1e9)
+        advance()
     torch.cuda.synchronize()
+    note(f"{prec}: warm-up done")
     ctx.cfl_dt(u)                        # surfaces a latched non-finite state
-    ader.ader_profile(ctx.ctx, True)
+    ader.ader_profile(ctx.ctx, not graph_steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        ctx.step(u, 1e9)
+        advance()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    note(f"{prec}: {steps} timed steps in {elapsed:.3f} s")
+    if graph_steps:  # stage times from profiled (not captured) steps after the timed region
+        ader.ader_profile(ctx.ctx, True)
+        for _ in range(graph_steps):
+            ctx.step(u, big)
     stages = ader.ader_stage_times(ctx.ctx)
     ader.ader_profile(ctx.ctx, False)
-    t_sim = float(ctx.time()[0])
+    t_sim = ctx.time()
+    try:            # the library's own check of the final state (NaN/Inf, rho <= 0, p <= 0)
+        ctx.cfl_dt(u)
+        finite = True
+    except ader.AderError:
+        finite = False
     ctx.close()
-    return dict(prob=prob, elapsed=elapsed, stages=stages, u=u, t_sim=t_sim, kernels=kernels,
-                value=prob.E * prob.nd * steps / elapsed)
+    dofs = sum(p.E * p.nd for p in probs)
+    per_step = max(1, graph_steps)
+    return dict(probs=probs, prob=probs[0], elapsed=elapsed, stages=stages, u=u, t_sim=float(t_sim.max()),
+                kernels=kernels, desc=desc, dofs=dofs, finite=finite,
+                value=dofs * steps * per_step / elapsed)
 
 
-def rel_l2_gpu(prob, a, b, I):
-    """max over variables of the discrete L2 norm of a-b relative to b."""
+def rel_l2_gpu(probs, a, b, I):
+    """max over problems and variables of the discrete L2 norm of a-b
+    relative to b (states of all problems concatenated).  The device only
+    reduces each element's nodes (one short contiguous sum per element and
+    variable); the sums over elements are finished on the host in FP64, so
+    no multi-workgroup device reduction is involved."""
+    import numpy as np
     import torch
-    W = torch.tensor(I.quad_weights(prob), device=a.device)
-    a3 = a.view(prob.E, prob.m, prob.nd)
-    b3 = b.view(prob.E, prob.m, prob.nd)
-    num = torch.einsum("evk,k->v", (a3 - b3) ** 2, W).sqrt()
-    den = torch.einsum("evk,k->v", b3 ** 2, W).sqrt()
-    return float((num / den).max().item())
+    worst, off = 0.0, 0
+    for prob in probs:
+        cnt = prob.E * prob.m * prob.nd
+        W = torch.tensor(I.quad_weights(prob), device=a.device)
+        a3 = a[off:off + cnt].view(prob.E, prob.m, prob.nd)
+        b3 = b[off:off + cnt].view(prob.E, prob.m, prob.nd)
+        num = ((a3 - b3) ** 2 * W).sum(dim=2).cpu().numpy().sum(axis=0)
+        den = (b3 ** 2 * W).sum(dim=2).cpu().numpy().sum(axis=0)
+        worst = max(worst, float(np.max(np.sqrt(num) / np.sqrt(den))))
+        off += cnt
+    return worst
 
 
 def stage_summary(res, trace_bytes):
-    prob = res["prob"]
-    per_el = step_bytes(3, prob.N, prob.m, trace_bytes)
     out = {}
     for k, (ms, cnt) in res["stages"].items():
-        avg = ms / max(1, cnt)
-        gbs = per_el[k] * prob.E / (avg * 1e-3) / 1e9 if avg > 0 else None
+        if not cnt:
+            continue
+        avg = ms / cnt
+        byts = sum(step_bytes(p.dim, p.N, p.m, trace_bytes)[k] * p.E for p in res["probs"])
+        gbs = byts / (avg * 1e-3) / 1e9 if avg > 0 else None
         out[k] = {"avg_ms": round(avg, 4), "alg_GB_per_s": round(gbs, 1) if gbs else None}
     return out
 
@@ -169,9 +272,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp64"],
                     help="precision of the headline path (compared against fp64)")
-    ap.add_argument("--nel", type=int, default=64)
-    ap.add_argument("--degree", type=int, default=4)
+    ap.add_argument("--workload", default="density", choices=["density", "elastic", "batched", "fourier"])
+    ap.add_argument("--nel", type=int, default=0, help="elements per axis (0: the workload's)")
+    ap.add_argument("--degree", type=int, default=-1, help="degree N (-1: the workload's)")
     ap.add_argument("--picard", type=int, default=0, help="Picard sweeps (0: N+1)")
+    ap.add_argument("--graph-steps", type=int, default=-1,
+                    help="steps per captured-graph replay (0: plain ader_step; -1: 10 for batched, else 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device copy (calibrates HBM byte counters)")
@@ -186,15 +292,19 @@ def main():
     from paper_1808_03788_amd import inputs as I
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    kw = dict(nel=args.nel, N=args.degree, picard=args.picard)
-    ref = run_path(kw, "fp64", args.steps, args.warmup, I, ader, torch)
-    head = ref if args.prec == "fp64" else run_path(kw, args.prec, args.steps, args.warmup, I, ader, torch)
-    prob = head["prob"]
-    err = 0.0 if head is ref else rel_l2_gpu(prob, head["u"], ref["u"], I)
-    finite = bool(torch.isfinite(head["u"]).all().item())
+    gs = args.graph_steps if args.graph_steps >= 0 else (10 if args.workload == "batched" else 0)
+    kw = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree, picard=args.picard,
+              graph_steps=gs)
+    ref = run_path(args.workload, "fp64", args.steps, args.warmup, I, ader, torch, **kw)
+    head = ref if args.prec == "fp64" else run_path(args.workload, args.prec, args.steps, args.warmup, I,
+                                                    ader, torch, **kw)
+    probs = head["probs"]
+    err = 0.0 if head is ref else rel_l2_gpu(probs, head["u"], ref["u"], I)
+    finite = head["finite"]
 
-    sweeps = prob.picard or prob.N + 1
-    flops = predictor_flops(3, prob.N, prob.m, sweeps) * prob.E
+    flops = sum(predictor_flops(p.dim, p.N, p.m, p.picard or p.N + 1, p.pde == "elastic") * p.E
+                for p in probs)
+
     def roof(res, prec):
         ms, cnt = res["stages"]["predictor"]
         pred_ms = ms / max(1, cnt)
@@ -213,11 +323,19 @@ def main():
             "peak": PEAK[peak_key],
             "unit": "TFLOP/s",
             "frac": round(achieved / PEAK[peak_key], 4),
-            "traffic": traffic_from_profiles(prec),
+            "traffic": traffic_from_profiles(prec) if args.workload == "density" and not args.nel else None,
             "alg_flops_per_launch": flops,
             "avg_launch_ms": round(pred_ms, 4),
         }
-    dofs = prob.E * prob.nd
+    per_step = max(1, gs)
+    prob = probs[0]
+    config = {"workload": head["desc"], "problems": len(probs),
+              "elements": sum(p.E for p in probs), "dofs": head["dofs"],
+              "variables": prob.m, "predictor_precision": args.prec}
+    if len(probs) == 1:
+        config.update(degree=prob.N, picard_sweeps=prob.picard or prob.N + 1)
+    else:
+        config.update(degrees=sorted({p.N for p in probs}), steps_per_replay=gs)
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -231,12 +349,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.prec == "fp64" else f"{args.prec}+f64",
         "data": "synthetic",
-        "config": {
-            "workload": f"3-D Euler density wave, periodic unit cube, {args.nel}^3 elements, "
-                        f"N={prob.N}, CFL 0.9, 1e-3 seeded noise",
-            "elements": prob.E, "degree": prob.N, "dofs": dofs, "variables": prob.m,
-            "picard_sweeps": sweeps, "predictor_precision": args.prec,
-        },
+        "config": config,
         "roofline": roof(head, args.prec),
         "fp64_path": {
             "value": ref["value"],
@@ -247,14 +360,18 @@ def main():
         },
         "speedup_vs_fp64": head["value"] / ref["value"],
         "rel_l2_vs_fp64_path": err,
-        "error_note": "max over variables of the relative discrete L2 difference to the FP64 "
-                      "GPU path after the same warmup+steps from the same state; the FP64 "
+        "error_note": "max over problems and variables of the relative discrete L2 difference to "
+                      "the FP64 GPU path after the same warmup+steps from the same state; the FP64 "
                       "path matches the FP64 oracle to <= 1e-12 (GPU parity tests)",
         "stages": stage_summary(head, 8 if args.prec == "fp64" else 4),
         "kernels": head["kernels"],
         "state_finite": finite,
         "sim_time": head["t_sim"],
     }
+    if per_step > 1:
+        line["timing_note"] = (f"a timed step is one captured-graph replay of {gs} steps of every "
+                               f"problem; value counts {gs} DOF-updates per DOF per replay; stages are "
+                               f"from {gs} profiled un-captured steps after the timed region")
     if args.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
@@ -263,7 +380,7 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+        line["cpu_baseline"] = cpu_baseline(args.workload)
     print(json.dumps(line), flush=True)
 
 

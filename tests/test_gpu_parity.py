@@ -89,7 +89,7 @@ def test_every_degree_2d(A, orc, N):
     check(prob, ug, uo, what=f"N={N}")
 
 
-@pytest.mark.parametrize("N", range(0, 6))
+@pytest.mark.parametrize("N", range(0, 8))
 def test_every_degree_3d(A, orc, N):
     prob = I.Problem(dim=3, N=N, nel=(3, 2, 4), lo=(0, 0, 0), hi=(1, 1, 1))
     u0 = I.density_wave(prob)

@@ -1,0 +1,92 @@
+"""Every predictor variant against the oracle.
+
+The autotuner picks one implementation per kernel class by timing, so any
+variant can end up on the path.  Here each one is forced (ADER_VARIANT, read
+at ader_create) on 3-D Euler for N = 2..7 and elasticity for N = 2..5 and
+held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-2
+(relative L2 after three steps).  A variant that does not fit the problem's
+LDS budget is not offered by the library and the case is skipped.
+"""
+import os
+import sys
+
+import pytest
+
+from paper_1808_03788_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1"],
+    "fp32": ["fp32-valu-b1", "fp32-valu-b2", "fp32-mfma-b1", "fp32-mfma-b2"],
+    "bf16": ["bf16-valu-b1", "bf16-valu-b2"],
+}
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
+CASES = [(pde, N, prec, v) for pde, Ns in (("euler", range(2, 8)), ("elastic", range(2, 6)))
+         for N in Ns for prec, vs in VARIANTS.items() for v in vs]
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_03788_amd import ader
+    ader.lib()
+    return ader
+
+
+_ref = {}
+
+
+def problem(pde, N, prec):
+    if pde == "euler":
+        p = I.Problem(dim=3, N=N, nel=(3, 2, 3), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec)
+        return p, I.density_wave(p)
+    p = I.elastic_problem(nel=2, N=N, prec=prec)
+    return p, I.stress_pulse(p, width=0.3)
+
+
+def oracle_ref(orc, pde, N):
+    if (pde, N) not in _ref:
+        p, u = problem(pde, N, "fp64")
+        t = 0.0
+        for _ in range(3):
+            u, t, _ = orc.step(p, u, t, 1e9)
+        _ref[(pde, N)] = u
+    return _ref[(pde, N)]
+
+
+@pytest.mark.parametrize("pde,N,prec,variant", CASES, ids=[f"{c[0]}-N{c[1]}-{c[3]}" for c in CASES])
+def test_forced_variant_vs_oracle(A, orc, pde, N, prec, variant):
+    import torch
+    prob, u0 = problem(pde, N, prec)
+    os.environ["ADER_VARIANT"] = variant
+    try:
+        ctx = A.Context([prob])
+    except A.AderError as e:
+        if e.status == A.ADER_ERR_UNSUPPORTED:
+            pytest.skip(f"not supported: {e}")
+        raise
+    finally:
+        del os.environ["ADER_VARIANT"]
+    try:
+        chosen = A.ader_describe(ctx.ctx, 0).split()[0].split("=")[1]
+        if chosen != variant:
+            pytest.skip(f"{variant} not offered for this problem (library chose {chosen})")
+        say(f"[variant] {pde} N={N} {variant}")
+        u = ctx.upload([u0])
+        for _ in range(3):
+            ctx.step(u, 1e9)
+        torch.cuda.synchronize()
+        ug = ctx.download(u)[0]
+    finally:
+        ctx.close()
+    err = I.rel_l2(prob, ug, oracle_ref(orc, pde, N))
+    say(f"  rel_l2={err:.3e}")
+    assert err <= TOL[prec], (variant, N, err)
