@@ -239,7 +239,8 @@ __device__ __forceinline__ float round_bf16(float x) {
 //   R -= (1/h_A) Dhat_A F_A(q)           (Euler)
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
 // Lines are enumerated over (l0, the other spatial indices).  With kRoundBF
-// the contraction inputs are rounded to bfloat16.
+// the contraction inputs are rounded to bfloat16.  With kConst only time
+// slice 0 is evaluated, and q and R are stored compactly as [M][ND].
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kConst>
 __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam,
                                          T mu) {
@@ -247,6 +248,7 @@ __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho,
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
   constexpr int NL = kConst ? NF : NST / n;  // a time-constant iterate: time slice 0 only
+  constexpr int VS = kConst ? ND : NST;      // stride of the variables
   for (int L = threadIdx.x; L < NL; L += BS) {
     const int l0 = L / NF, r = L - l0 * NF;
     const int lo = r % ST, hi = r / ST;
@@ -255,13 +257,13 @@ __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho,
 #pragma unroll
     for (int j = 0; j < n; j++)
 #pragma unroll
-      for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * NST + base + j * ST];
+      for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * VS + base + j * ST];
     // the accumulated right-hand side of the earlier axes
     T acc[n][M];
 #pragma unroll
     for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) acc[k][v] = A == 0 ? T(0) : sacc[v * NST + base + k * ST];
+      for (int v = 0; v < M; v++) acc[k][v] = A == 0 ? T(0) : sacc[v * VS + base + k * ST];
     if constexpr (!PDE::kElastic) {
       T F[n][M];
 #pragma unroll
@@ -301,7 +303,7 @@ __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho,
 #pragma unroll
     for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) sacc[v * NST + base + k * ST] = acc[k][v];
+      for (int v = 0; v < M; v++) sacc[v * VS + base + k * ST] = acc[k][v];
   }
 }
 
@@ -342,7 +344,8 @@ __device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout,
       const T u0 = (T)ureg[r];
       if constexpr (kConst) {
         // R is the same at every time node: sum_j T[l][j] R = Trow[l] R
-        const T r0 = sacc[v * NST + k];
+        // (R stored compactly as [M][ND])
+        const T r0 = sacc[v * ND + k];
 #pragma unroll
         for (int l = 0; l < n; l++) qout[v * NST + l * ND + k] = (TO)(u0 + dt * (opTrow<T>(P, l) * r0));
       } else {
@@ -606,13 +609,18 @@ __device__ __forceinline__ void euler_volume_axis(PArg &P, double *FB) {
   }
 }
 
-// u* = u + dt V from the accumulated volume term V[v][k] (one thread per DOF).
+// u* = u + dt V from the accumulated volume term V[v][k] (one thread per
+// DOF; DOF threadIdx.x + r*BS is the one whose u the thread holds in ureg[r]).
 template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void ustar_update(const double *V, const double *ue, double *us, double dt) {
+__device__ __forceinline__ void ustar_update(const double *V, const double *ureg, double *us, double dt) {
   constexpr int M = PDE::M, ND = Shape<D, N>::ND;
-  for (int i = threadIdx.x; i < M * ND; i += BS)
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
     // dt = 0 (flagged state or t already at t_end) leaves the state untouched
-    us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V[i];
+    if (i < M * ND) us[i] = dt == 0.0 ? ureg[r] : ureg[r] + dt * V[i];
+  }
 }
 
 // Elastic volume term (one thread per node), fused with u* = u + dt V:
@@ -695,8 +703,8 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
 // u* = u + dt V.
 template <int D, int N, class PDE, typename TT, int BS>
 __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, double *scratch,
-                                                  const double *ue, double dt, int64_t e, double *qo,
-                                                  double irho, double lam, double mu) {
+                                                  const double *ue, const double *ureg, double dt, int64_t e,
+                                                  double *qo, double irho, double lam, double mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   if (qo)
@@ -720,7 +728,7 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
       euler_volume_axis<D, N, PDE, 2, BS>(P, scratch);
       __syncthreads();
     }
-    ustar_update<D, N, PDE, BS>(scratch, ue, us, dt);
+    ustar_update<D, N, PDE, BS>(scratch, ureg, us, dt);
   } else {
     for (int i = threadIdx.x; i < M * ND; i += BS) {
       const int v = i / ND, k = i - v * ND;
@@ -731,6 +739,20 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
     }
     __syncthreads();
     elastic_volume_update<D, N, BS>(P, scratch, ue, us, dt, irho, lam, mu);
+  }
+}
+
+// q^0 = u (as TQ) in the compact [M][ND] layout of the time-constant first
+// sweep, from the u values each thread keeps in registers (ureg[r] holds
+// u[i], i = threadIdx.x + r*BS).
+template <int D, int N, class PDE, typename TQ, int BS>
+__device__ __forceinline__ void stage_slice0(TQ *sq, const double *ureg) {
+  constexpr int M = PDE::M, ND = Shape<D, N>::ND;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    if (i < M * ND) sq[i] = (TQ)ureg[r];
   }
 }
 
@@ -765,30 +787,34 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
   if constexpr (PREC == kFP64) {
     double *sq = (double *)smem_raw;
     double *sacc = kAccLds ? (double *)(smem_raw + L::A) : P.acc_glob + e * (int64_t)(M * S::ACC);
-    // q^0 = u_h(t^n), constant in time (K1^{-1} F0 = 1)
-    for (int i = threadIdx.x; i < M * ND; i += BS) {
-      const double val = ue[i];
-      const int v = i / ND, k = i - v * ND;
-#pragma unroll
-      for (int l0 = 0; l0 < n; l0++) sq[v * NST + l0 * ND + k] = val;
-    }
+    // q^0 = u_h(t^n), constant in time (K1^{-1} F0 = 1): the first sweep
+    // reads only its time slice 0
+    stage_slice0<D, N, PDE, double, BS>(sq, ureg);
     __syncthreads();
     // the first sweep starts from the time-constant iterate q^0 = u
     picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
     for (int s = 1; s < P.sweeps; s++)
       picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, dt, e, qo, irho, lam, mu);
+    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, ureg, dt, e, qo, irho, lam, mu);
   } else {
     constexpr bool kBF = PREC == kBF16;
     float *sq32 = (float *)smem_raw;
     double *sR = (double *)(smem_raw + L::A);
     float *sacc32 = (float *)sR;
-    for (int i = threadIdx.x; i < M * ND; i += BS) {
-      const float val = (float)ue[i];
-      const int v = i / ND, k = i - v * ND;
-#pragma unroll
-      for (int l0 = 0; l0 < n; l0++) sq32[v * NST + l0 * ND + k] = val;
+    if (P.sweeps == 1) {
+      // a single sweep is the FP64 one, from q^0 = u itself: region A holds
+      // u and the right-hand side (compact [M][ND] each, 2*M*ND doubles fit),
+      // the sweep's iterate lands in region R
+      static_assert(2 * M * ND * 8 <= L::A, "region A holds two compact slices");
+      double *su = (double *)smem_raw;
+      stage_slice0<D, N, PDE, double, BS>(su, ureg);
+      __syncthreads();
+      picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, su, su + M * ND, sR, ureg, dt, irho,
+                                                                       lam, mu);
+      predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
+      return;
     }
+    stage_slice0<D, N, PDE, float, BS>(sq32, ureg);
     __syncthreads();
     const float dtf = (float)dt;
     if constexpr (PREC == kFP32 && kMfma) {
@@ -803,15 +829,15 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
           Db[c][j] = k < n ? cload(&P.sw->Df[k * kMaxN + j]) : 0.f;
           Tb[c][j] = k < n ? cload(&P.sw->Tf[k * kMaxN + j]) : 0.f;
         }
-      if (P.sweeps > 1)  // first sweep from the time-constant iterate q^0 = u
-        picard_sweep<D, N, PDE, float, float, float, false, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
-                                                                      (float)irho, (float)lam, (float)mu);
+      // first sweep from the time-constant iterate q^0 = u
+      picard_sweep<D, N, PDE, float, float, float, false, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                    (float)irho, (float)lam, (float)mu);
       for (int s = 1; s + 1 < P.sweeps; s++)
         picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
     } else {
-      if (P.sweeps > 1)  // first sweep from the time-constant iterate q^0 = u
-        picard_sweep<D, N, PDE, float, float, float, kBF, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
-                                                                    (float)irho, (float)lam, (float)mu);
+      // first sweep from the time-constant iterate q^0 = u
+      picard_sweep<D, N, PDE, float, float, float, kBF, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                  (float)irho, (float)lam, (float)mu);
       for (int s = 1; s + 1 < P.sweeps; s++)
         picard_sweep<D, N, PDE, float, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho,
                                                           (float)lam, (float)mu);
@@ -819,7 +845,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
     // the FP64 accumulator in place
     picard_sweep<D, N, PDE, double, float, double, false, BS>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, dt, e, qo, irho, lam, mu);
+    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
   }
 }
 

@@ -342,3 +342,17 @@ def test_fp32_design_order_vortex(A):
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     say(f"[fp32] vortex errors {errs} orders {orders}")
     assert orders[-1] > 3.6
+
+
+@pytest.mark.parametrize("picard", [1, 2, 3])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_picard_counts(A, orc, prec, picard):
+    """Fewer Picard sweeps than N+1 (the first sweep from the time-constant
+    iterate, and the single-sweep case where it is the FP64 one)."""
+    mk = lambda pr: I.Problem(dim=3, N=3, nel=(3, 4, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr, picard=picard)
+    prob = mk(prec)
+    u0 = I.density_wave(prob)
+    say(f"[picard] {prec} P={picard}")
+    ug, _ = gpu_run(A, prob, u0, 3)
+    uo, _ = orc_run(orc, mk("fp64"), u0, 3)
+    check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{prec} P={picard}")
