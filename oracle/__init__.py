@@ -155,6 +155,14 @@ def predictor(prob, u: np.ndarray, dt: float) -> np.ndarray:
     return q
 
 
+def initial_guess(prob, u: np.ndarray, dt: float) -> np.ndarray:
+    """The Picard iteration's initial guess q^0[E][m][n][n^d] selected by
+    prob.guess (no sweep)."""
+    q, used = predictor_converge(prob, u, dt, 0.0, 0)
+    assert used == 0
+    return q
+
+
 def predictor_converge(prob, u: np.ndarray, dt: float, tol: float, max_sweeps: int):
     b = _Bound(prob)
     u = np.ascontiguousarray(u, dtype=np.float64)

@@ -229,6 +229,7 @@ typedef struct {
 
 static int setup(const orc_problem *p, setup_t *s) {
   if (p->dim < 1 || p->dim > 3 || p->N < 0 || p->N + 1 > ORC_MAXN) return -1;
+  if (p->guess < 0 || p->guess > 2) return -1;
   if (p->pde == ORC_ELASTIC && (p->dim != 3 || !p->material)) return -1;
   s->d = p->dim;
   s->n = p->N + 1;
@@ -363,18 +364,57 @@ static void predictor_rhs(const orc_problem *p, const setup_t *s, const double *
     }
 }
 
-/* Picard iteration of one element (reading: initial guess q^0 = u_h(t^n)
- * constant in time, a fixed number of sweeps):
- *   q^{r}(l0,k) = u(k) + dt * sum_j0 T[l0][j0] R(q^{r-1})(j0,k).
- * Returns the number of sweeps done; stops early only when tol > 0 and the
- * update fell to tol * max|q|. */
+/* L(w) = S - div F - B.grad of a state w(k) constant in time, at the
+ * spatial nodes: the collocated right-hand side of the time-constant
+ * space-time polynomial (all its time slices are equal; slice 0 is kept). */
+static void rhs_of_state(const orc_problem *p, const setup_t *s, const double *mat,
+                         const double *w, double *q, double *F, double *R, double *out) {
+  int m = s->m, nd = s->nd, n = s->n;
+  for (int v = 0; v < m; v++)
+    for (int l0 = 0; l0 < n; l0++)
+      for (int k = 0; k < nd; k++) q[(v * n + l0) * nd + k] = w[v * nd + k];
+  predictor_rhs(p, s, mat, q, F, R);
+  for (int v = 0; v < m; v++)
+    for (int k = 0; k < nd; k++) out[v * nd + k] = R[(v * n + 0) * nd + k];
+}
+
+int orc_sweeps(const orc_problem *p) {
+  if (p->picard > 0) return p->picard;
+  int g = p->guess > 0 ? p->guess : 0;
+  return p->N + 1 - g > 1 ? p->N + 1 - g : 1;
+}
+
+/* Picard iteration of one element (Sec. 2.2), a fixed number of sweeps
+ *   q^{r}(l0,k) = u(k) + dt * sum_j0 T[l0][j0] R(q^{r-1})(j0,k),
+ * from the initial guess q^0 selected by p->guess (evaluated at the time
+ * nodes t = t^n + xi_l0 dt, see orc_problem).  Returns the number of sweeps
+ * done; stops early only when tol > 0 and the update fell to tol * max|q|. */
 static int element_predictor(const orc_problem *p, const setup_t *s, const double *mat,
                              const double *ue, double dt, int sweeps, double tol,
                              double *q, double *F, double *R) {
   int m = s->m, nd = s->nd, n = s->n;
-  for (int v = 0; v < m; v++)
-    for (int l0 = 0; l0 < n; l0++)
-      for (int k = 0; k < nd; k++) q[(v * n + l0) * nd + k] = ue[v * nd + k];
+  if (p->guess == 0) {
+    for (int v = 0; v < m; v++)
+      for (int l0 = 0; l0 < n; l0++)
+        for (int k = 0; k < nd; k++) q[(v * n + l0) * nd + k] = ue[v * nd + k];
+  } else {
+    double k1[MAXM * ORC_MAXN * ORC_MAXN * ORC_MAXN], k2[MAXM * ORC_MAXN * ORC_MAXN * ORC_MAXN];
+    rhs_of_state(p, s, mat, ue, q, F, R, k1);
+    if (p->guess == 2) {
+      double w[MAXM * ORC_MAXN * ORC_MAXN * ORC_MAXN];
+      for (int i = 0; i < m * nd; i++) w[i] = ue[i] + dt * k1[i];
+      rhs_of_state(p, s, mat, w, q, F, R, k2);
+    }
+    for (int v = 0; v < m; v++)
+      for (int l0 = 0; l0 < n; l0++)
+        for (int k = 0; k < nd; k++) {
+          const int i = v * nd + k;
+          const double tau = s->xi[l0] * dt;  /* t - t^n */
+          double g = ue[i] + tau * k1[i];
+          if (p->guess == 2) g += tau * tau * (k2[i] - k1[i]) / (2.0 * dt);
+          q[(v * n + l0) * nd + k] = g;
+        }
+  }
   int r;
   for (r = 1; r <= sweeps; r++) {
     predictor_rhs(p, s, mat, q, F, R);
@@ -425,7 +465,7 @@ static int run_predictor(const orc_problem *p, const double *u, double dt, int s
 }
 
 int orc_predictor(const orc_problem *p, const double *u, double dt, double *qhat) {
-  int sweeps = p->picard > 0 ? p->picard : p->N + 1;
+  int sweeps = orc_sweeps(p);
   return run_predictor(p, u, dt, sweeps, 0.0, qhat) < 0 ? -1 : 0;
 }
 

@@ -43,10 +43,20 @@ typedef struct {
   int pde;          /* ORC_EULER or ORC_ELASTIC */
   double gamma;     /* Euler: ratio of specific heats */
   const double *material; /* ELASTIC: [E][3] = (rho, lambda, mu) */
-  int picard;       /* number of Picard sweeps; 0 -> N+1 */
+  int picard;       /* number of Picard sweeps; 0 -> max(1, N+1-guess) */
   double cfl;       /* dt = cfl*alpha_N / max_e sum_d lambda_d/h_d */
-  int guess;        /* initial guess of the Picard iteration: 0 = u_h(t^n) */
+  int guess;        /* initial guess of the Picard iteration (Sec. 2.2):
+                       0  q0 = u_h(t^n), constant in time;
+                       1  second-order MUSCL-Hancock type
+                          q0(t) = u + (t - t^n) L(u);
+                       2  third-order Taylor type
+                          q0(t) = u + (t - t^n) k1 + (t - t^n)^2 (k2 - k1) / (2 dt),
+                          k1 = L(u), k2 = L(u + dt k1);
+                       L = S - div F - B.grad, the collocated right-hand side. */
 } orc_problem;
+
+/* Picard sweeps used for a problem: picard, or max(1, N+1-guess). */
+int orc_sweeps(const orc_problem *p);
 
 /* 1-D basis on [0,1] (Sec. 2.1). */
 int orc_gauss_legendre(int n, double *xi, double *w);

@@ -388,6 +388,53 @@ def test_order_elastic_plane_waves(orc, N):
     assert _order(errs)[0] > N + 1 - 0.2, errs
 
 
+# ---------------------------------------------- initial guesses (Sec. 2.2)
+
+@pytest.mark.parametrize("guess", [0, 1, 2])
+def test_initial_guess_order_in_time(orc, guess):
+    """The guess q^0 against the converged Picard fixed point q* of the same
+    step: the MUSCL-Hancock type guess is a first-order Taylor polynomial in
+    time and the third-order one a second-order polynomial, so
+    max|q^0 - q*| falls like dt^(guess+1) when dt is halved (the fixed point
+    itself is accurate to a higher order at N = 3)."""
+    prob = I.Problem(dim=3, N=3, nel=(2, 2, 2), lo=(0,) * 3, hi=(1,) * 3, guess=guess)
+    u = I.density_wave(prob, noise=0)
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        q0 = orc.initial_guess(prob, u, dt)
+        qs, used = orc.predictor_converge(prob, u, dt, 1e-15, 60)
+        assert used < 60
+        errs.append(np.abs(q0 - qs).max())
+    o = _order(errs)
+    assert abs(o[-1] - (guess + 1)) < 0.25, (errs, o)
+
+
+@pytest.mark.parametrize("N", [1, 3, 5])
+def test_muscl_guess_equals_one_more_sweep(orc, N):
+    """For N >= 1 the first sweep from the constant guess is exactly the
+    MUSCL-Hancock type guess (T integrates a constant right-hand side
+    exactly: its row sums are the time nodes), so guess 1 with P sweeps and
+    guess 0 with P+1 sweeps agree to rounding."""
+    kw = dict(dim=3, N=N, nel=(2, 3, 2), lo=(0,) * 3, hi=(1,) * 3)
+    u = I.density_wave(I.Problem(**kw))
+    dt = 1e-3
+    a = orc.predictor(I.Problem(picard=2, guess=1, **kw), u, dt)
+    b = orc.predictor(I.Problem(picard=3, guess=0, **kw), u, dt)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
+
+
+@pytest.mark.parametrize("N,meshes", [(2, (8, 16)), (3, (4, 8))])
+def test_order_with_third_order_guess(orc, N, meshes):
+    """The scheme with the third-order guess and its default max(1, N-1)
+    sweeps keeps the design order N+1 on the density wave."""
+    errs = []
+    for nel in meshes:
+        prob = I.density_wave_problem(nel=nel, N=N, guess=2)
+        u, t, _ = orc.run(prob, I.density_wave(prob, noise=0), 0.0, 0.05)
+        errs.append(I.l2_per_var(prob, u - I.density_wave(prob, t=t, noise=0))[0])
+    assert _order(errs)[0] > N + 1 - 0.4, errs
+
+
 def test_last_step_lands_on_t_end(orc):
     prob = I.vortex_problem(nel=4, N=1)
     u, t, steps = orc.run(prob, I.isentropic_vortex(prob), 0.0, 0.637)
