@@ -40,30 +40,49 @@ PEAK = {"fp64_valu": 78.6, "fp32_valu": 78.6, "fp32_mfma": 157.3, "bf16_mfma": 2
 
 
 def predictor_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False, cF: int = 31,
-                    cB: int = 15) -> float:
+                    cB: int = 15, guess: int = 0) -> float:
     """Algorithmic (sum-factorised) flops of the predictor for one element,
     counting a multiply-add as 2 flops and a division as 1.
-    Euler (m = d+2):
-      per sweep: cF flux flops per space-time node (the primitive variables
-        once, 7 flops per axis), d axis contractions and 1 time contraction
-        at 2n flops per output, and 2 flops per output for u + dt * (...);
-      outputs: one more flux evaluation, the time average (2 flops per
-        output and axis), the volume contraction (2n per output and axis),
-        u* = u + dt V and the 2d face traces (2n per trace value).
-    Elasticity (m = 9): the flux evaluation is replaced by cB flops per
-      space-time node and axis for B_A (Dhat q) (velocity rows 3, stress
-      rows 12); the volume term contracts the time average (2n per value)
-      and applies B_A once per spatial node and axis."""
+    A full sweep (Euler, m = d+2): cF flux flops per space-time node (the
+      primitive variables once, 7 flops per axis), d axis contractions and 1
+      time contraction at 2n flops per output, and 2 flops per output for
+      u + dt * (...).  Elasticity (m = 9): the flux evaluation is replaced
+      by cB flops per space-time node and axis for B_A (Dhat q) (velocity
+      rows 3, stress rows 12).
+    Initial guess: from the constant guess the first sweep needs the
+      right-hand side on one time slice only (its value is the same at every
+      time node) and 2 flops per space-time value, then sweeps-1 full
+      sweeps; guess 1 (2) takes one (two) such slice right-hand sides, 2
+      flops per node value for u + dt k1 (guess 2) and 3 (5) flops per
+      space-time value for the Taylor polynomial, then `sweeps` full sweeps.
+    Outputs (Euler): one more flux evaluation, the time average (2 flops per
+      output and axis), the volume contraction (2n per output and axis),
+      u* = u + dt V and the 2d face traces (2n per trace value); elasticity:
+      the time average (2n per value) and B_A once per spatial node and axis
+      in the volume term."""
     n = N + 1
     nst = n ** (d + 1)
     nd = n ** d
     if not elastic:
         sweep = cF * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
+        slice_rhs = cF * nd + d * 2 * n * m * nd
         outputs = cF * nst + 2 * m * d * nst + d * 2 * n * m * nd + 2 * m * nd + 2 * d * 2 * n * m * nd
     else:
         sweep = d * cB * nst + (d + 1) * 2 * n * m * nst + 2 * m * nst
+        slice_rhs = d * cB * nd + d * 2 * n * m * nd
         outputs = 2 * n * m * nd + d * (2 * n * m * nd + cB * nd) + 2 * m * nd + 2 * d * 2 * n * m * nd
-    return sweeps * sweep + outputs
+    if guess == 0:
+        start, full = slice_rhs + 2 * m * nst, sweeps - 1
+    elif guess == 1:
+        start, full = slice_rhs + 3 * m * nst, sweeps
+    else:
+        start, full = 2 * slice_rhs + 2 * m * nd + 5 * m * nst, sweeps
+    return start + full * sweep + outputs
+
+
+def sweeps_of(p) -> int:
+    """Picard sweeps of a problem: picard, or max(1, N+1-guess)."""
+    return p.picard or max(1, p.N + 1 - (p.guess or 0))
 
 
 def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
@@ -107,7 +126,7 @@ def traffic_from_profiles(prec: str):
     return rec.get(prec, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(workload: str = "density", seconds: float = 12.0) -> dict:
+def cpu_baseline(workload: str = "density", seconds: float = 12.0, guess: int = 0) -> dict:
     """The FP64 oracle on a bounded sample of the workload (same degree,
     PDE and initial-data recipe on a smaller mesh, or a few of the batched
     problems), as many steps as fit in about `seconds` (at least one)."""
@@ -116,11 +135,13 @@ def cpu_baseline(workload: str = "density", seconds: float = 12.0) -> dict:
     if workload == "batched":
         items = sorted(I.batched_problems(count=256, seed=0, prec="fp64"), key=lambda it: it[0].E * it[0].nd)[:8]
         probs = [p for p, _ in items]
+        for p in probs:
+            p.guess = guess
         us = [I.density_wave(p, **kw) for p, kw in items]
         what = "the 8 smallest of the 256 batched problems"
     else:
         probs, us, _ = make_workload(workload, "fp64", I, nel={"density": 16, "elastic": 12,
-                                                               "fourier": 32}[workload])
+                                                               "fourier": 32}[workload], guess=guess)
         what = f"{probs[0].nel[0]}^3 elements of the same recipe"
     ts = [0.0] * len(probs)
     steps = 0
@@ -148,30 +169,32 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(workload, prec, I, nel=None, degree=None, picard=0):
+def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0):
     """(problems, initial states, description) of a workload."""
     if workload == "density":
         prob = I.density_wave_problem(nel=nel or 64, N=4 if degree is None else degree, prec=prec,
-                                      picard=picard)
+                                      picard=picard, guess=guess)
         desc = (f"3-D Euler density wave, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
                 f"CFL 0.9, 1e-3 seeded noise")
         return [prob], [I.density_wave(prob)], desc
     if workload == "elastic":
-        prob = I.elastic_problem(nel=nel or 48, N=5 if degree is None else degree, prec=prec, picard=picard)
+        prob = I.elastic_problem(nel=nel or 48, N=5 if degree is None else degree, prec=prec, picard=picard,
+                                 guess=guess)
         desc = (f"3-D linear elasticity, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
                 f"4 seeded layers (rho 2000-3000, cp 3000-6000, cs = cp/sqrt 3), stress pulse width 0.05")
         return [prob], [I.stress_pulse(prob)], desc
     if workload == "fourier":
-        prob = I.fourier_problem(nel=nel or 128, N=3 if degree is None else degree, prec=prec, picard=picard)
+        prob = I.fourier_problem(nel=nel or 128, N=3 if degree is None else degree, prec=prec, picard=picard,
+                                 guess=guess)
         desc = (f"3-D Euler, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, 8 seeded Fourier "
                 f"modes of amplitude 0.05 on rho = 1, p = 1")
         return [prob], [I.fourier_modes(prob)], desc
     if workload == "batched":
         items = I.batched_problems(count=256, seed=0, prec=prec)
         probs = [p for p, _ in items]
-        if picard:
-            for p in probs:
-                p.picard = picard
+        for p in probs:
+            p.picard = picard
+            p.guess = guess
         inits = [I.density_wave(p, **kw) for p, kw in items]
         desc = ("256 seeded 3-D Euler density waves, meshes 8^3..32^3, N in 2..6, one context, "
                 "batched launches per degree, captured-graph replays")
@@ -180,11 +203,11 @@ def make_workload(workload, prec, I, nel=None, degree=None, picard=0):
 
 
 def run_path(workload, prec, steps, warmup, I, ader, torch, nel=None, degree=None, picard=0,
-             graph_steps=0):
+             graph_steps=0, guess=0):
     """Time `steps` steps (or graph replays of `graph_steps` steps each) of
     one precision mode; returns the timings, stage times and the final state
     (device tensor)."""
-    probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard)
+    probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard, guess)
     note(f"{prec}: {len(probs)} problem(s) generated")
     ctx = ader.Context(probs)
     note(f"{prec}: context created ({ader.ader_describe(ctx.ctx, 0).split()[0]})")
@@ -275,7 +298,9 @@ def main():
     ap.add_argument("--workload", default="density", choices=["density", "elastic", "batched", "fourier"])
     ap.add_argument("--nel", type=int, default=0, help="elements per axis (0: the workload's)")
     ap.add_argument("--degree", type=int, default=-1, help="degree N (-1: the workload's)")
-    ap.add_argument("--picard", type=int, default=0, help="Picard sweeps (0: N+1)")
+    ap.add_argument("--picard", type=int, default=0, help="Picard sweeps (0: max(1, N+1-guess))")
+    ap.add_argument("--guess", type=int, default=0, choices=[0, 1, 2],
+                    help="initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type")
     ap.add_argument("--graph-steps", type=int, default=-1,
                     help="steps per captured-graph replay (0: plain ader_step; -1: 10 for batched, else 0)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -294,7 +319,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gs = args.graph_steps if args.graph_steps >= 0 else (10 if args.workload == "batched" else 0)
     kw = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree, picard=args.picard,
-              graph_steps=gs)
+              graph_steps=gs, guess=args.guess)
     ref = run_path(args.workload, "fp64", args.steps, args.warmup, I, ader, torch, **kw)
     head = ref if args.prec == "fp64" else run_path(args.workload, args.prec, args.steps, args.warmup, I,
                                                     ader, torch, **kw)
@@ -302,7 +327,7 @@ def main():
     err = 0.0 if head is ref else rel_l2_gpu(probs, head["u"], ref["u"], I)
     finite = head["finite"]
 
-    flops = sum(predictor_flops(p.dim, p.N, p.m, p.picard or p.N + 1, p.pde == "elastic") * p.E
+    flops = sum(predictor_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic", guess=p.guess) * p.E
                 for p in probs)
 
     def roof(res, prec):
@@ -333,7 +358,7 @@ def main():
               "elements": sum(p.E for p in probs), "dofs": head["dofs"],
               "variables": prob.m, "predictor_precision": args.prec}
     if len(probs) == 1:
-        config.update(degree=prob.N, picard_sweeps=prob.picard or prob.N + 1)
+        config.update(degree=prob.N, picard_sweeps=sweeps_of(prob), initial_guess=prob.guess)
     else:
         config.update(degrees=sorted({p.N for p in probs}), steps_per_replay=gs)
     line = {
@@ -380,7 +405,7 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload)
+        line["cpu_baseline"] = cpu_baseline(args.workload, guess=args.guess)
     print(json.dumps(line), flush=True)
 
 

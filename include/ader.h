@@ -75,8 +75,14 @@ typedef struct {
   const double *material; /* ELASTIC: HOST array [E][3] = (rho, lambda, mu),
                              copied at create; ignored for Euler */
   int32_t prec;         /* ader_prec */
-  int32_t picard_iters; /* Picard sweeps P; 0 -> N+1 */
+  int32_t picard_iters; /* Picard sweeps P; 0 -> max(1, N+1-guess) */
   double cfl;           /* dt = cfl * alpha_N / max_e sum_d lambda_d / h_d,  0 < cfl <= 1 */
+  int32_t guess;        /* initial guess of the Picard iteration (Sec. 2.2), a Taylor
+                           polynomial in t - t^n at the time nodes: 0 q0 = u (constant);
+                           1 q0 = u + (t-t^n) L(u) (MUSCL-Hancock type, second order);
+                           2 q0 = u + (t-t^n) k1 + (t-t^n)^2 (k2-k1)/(2 dt), k1 = L(u),
+                           k2 = L(u + dt k1) (third order); L = S - div F - B.grad.
+                           Guesses 1 and 2 are computed in the sweeps' precision. */
 } ader_problem;
 
 /* Create a context for `nprob` independent problems (Sec. 2; the problems

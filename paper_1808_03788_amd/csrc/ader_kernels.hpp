@@ -165,6 +165,8 @@ struct OpsSweep {
   float Trowf[kMaxN];
   float Df[kMaxN * kMaxN];   // unscaled Dhat (MFMA operands, scaled after the contraction)
   double VA[3][kMaxN * kMaxN];  // (1/h_A) V: volume operator of axis A
+  double xi[kMaxN];             // time nodes (initial guesses)
+  float xif[kMaxN];
 };
 
 struct PredArgs {
@@ -180,6 +182,7 @@ struct PredArgs {
                         // double for FP64, float for the mixed modes
   double *acc_glob;     // FP64 accumulator when it does not fit in LDS: [E][M][ACC]
   int sweeps;
+  int guess;            // initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type
 };
 // Argument records are read in place through the constant address space:
 // every field load is a scalar load, whatever the kernel has written.
@@ -209,7 +212,9 @@ struct PredLds {
       PREC == kFP64 ? (size_t)M * S::NST * 8
                     : ((size_t)M * S::NST * 4 > (size_t)D * M * S::ND * 8 ? (size_t)M * S::NST * 4
                                                                             : (size_t)D * M * S::ND * 8));
-  static constexpr size_t R = round256(PREC == kFP64 ? (size_t)M * S::ACC * 8 : (size_t)M * S::NST * 8);
+  // (M * ACC doubles: the space-time accumulator or FP64 iterate, and at
+  // least the D per-axis parts of a one-slice right-hand side)
+  static constexpr size_t R = round256((size_t)M * S::ACC * 8);
 };
 
 // Threads per workgroup of the predictor: the number of lines of one axis
@@ -234,76 +239,109 @@ __device__ __forceinline__ float round_bf16(float x) {
   return __uint_as_float(b & 0xffff0000u);
 }
 
-// Collocated right-hand side along axis A for all lines of the element, in
-// arithmetic T, reading q stored as TQ:
+// Collocated right-hand side along axis A on one line of n nodes (starting
+// at offset `base`, stride n^A; variables VS apart), in arithmetic T, reading
+// q stored as TQ:
 //   R -= (1/h_A) Dhat_A F_A(q)           (Euler)
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
-// Lines are enumerated over (l0, the other spatial indices).  With kRoundBF
-// the contraction inputs are rounded to bfloat16.  With kConst only time
-// slice 0 is evaluated, and q and R are stored compactly as [M][ND].
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kConst>
-__device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam,
-                                         T mu) {
-  using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
+// With kAcc the result is added to the values already in sacc, else it is
+// stored.  With kRoundBF the contraction inputs are rounded to bfloat16.
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc>
+__device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu) {
+  constexpr int n = N + 1, M = PDE::M;
   constexpr int ST = ipow(n, A);
-  constexpr int NL = kConst ? NF : NST / n;  // a time-constant iterate: time slice 0 only
-  constexpr int VS = kConst ? ND : NST;      // stride of the variables
-  for (int L = threadIdx.x; L < NL; L += BS) {
-    const int l0 = L / NF, r = L - l0 * NF;
-    const int lo = r % ST, hi = r / ST;
-    const int base = l0 * ND + lo + hi * ST * n;
-    T qv[n][M];
+  T qv[n][M];
 #pragma unroll
-    for (int j = 0; j < n; j++)
+  for (int j = 0; j < n; j++)
 #pragma unroll
-      for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * VS + base + j * ST];
-    // the accumulated right-hand side of the earlier axes
-    T acc[n][M];
+    for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * VS + base + j * ST];
+  // the accumulated right-hand side of the earlier axes
+  T acc[n][M];
 #pragma unroll
-    for (int k = 0; k < n; k++)
+  for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) acc[k][v] = A == 0 ? T(0) : sacc[v * VS + base + k * ST];
-    if constexpr (!PDE::kElastic) {
-      T F[n][M];
+    for (int v = 0; v < M; v++) acc[k][v] = kAcc ? sacc[v * VS + base + k * ST] : T(0);
+  if constexpr (!PDE::kElastic) {
+    T F[n][M];
 #pragma unroll
-      for (int j = 0; j < n; j++) {
-        euler_flux<D, A, T>(qv[j], (T)(P.g.gamma - 1.0), F[j]);
-        if constexpr (kRoundBF)
-#pragma unroll
-          for (int v = 0; v < M; v++) F[j][v] = round_bf16(F[j][v]);
-      }
-#pragma unroll
-      for (int k = 0; k < n; k++)
-#pragma unroll
-        for (int v = 0; v < M; v++)
-#pragma unroll
-          for (int j = 0; j < n; j++) acc[k][v] += opD<T>(P, A, k * kMaxN + j) * F[j][v];
-    } else {
+    for (int j = 0; j < n; j++) {
+      euler_flux<D, A, T>(qv[j], (T)(P.g.gamma - 1.0), F[j]);
       if constexpr (kRoundBF)
 #pragma unroll
-        for (int j = 0; j < n; j++)
-#pragma unroll
-          for (int v = 0; v < M; v++) qv[j][v] = round_bf16(qv[j][v]);
-#pragma unroll
-      for (int k = 0; k < n; k++) {
-        T gk[M], bg[M];
-#pragma unroll
-        for (int v = 0; v < M; v++) {
-          T s = T(0);
-#pragma unroll
-          for (int j = 0; j < n; j++) s += opD<T>(P, A, k * kMaxN + j) * qv[j][v];
-          gk[v] = s;
-        }
-        elastic_bg<A, T>(gk, irho, lam, mu, bg);
-#pragma unroll
-        for (int v = 0; v < M; v++) acc[k][v] += bg[v];
-      }
+        for (int v = 0; v < M; v++) F[j][v] = round_bf16(F[j][v]);
     }
 #pragma unroll
     for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) sacc[v * VS + base + k * ST] = acc[k][v];
+      for (int v = 0; v < M; v++)
+#pragma unroll
+        for (int j = 0; j < n; j++) acc[k][v] += opD<T>(P, A, k * kMaxN + j) * F[j][v];
+  } else {
+    if constexpr (kRoundBF)
+#pragma unroll
+      for (int j = 0; j < n; j++)
+#pragma unroll
+        for (int v = 0; v < M; v++) qv[j][v] = round_bf16(qv[j][v]);
+#pragma unroll
+    for (int k = 0; k < n; k++) {
+      T gk[M], bg[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        T s = T(0);
+#pragma unroll
+        for (int j = 0; j < n; j++) s += opD<T>(P, A, k * kMaxN + j) * qv[j][v];
+        gk[v] = s;
+      }
+      elastic_bg<A, T>(gk, irho, lam, mu, bg);
+#pragma unroll
+      for (int v = 0; v < M; v++) acc[k][v] += bg[v];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < n; k++)
+#pragma unroll
+    for (int v = 0; v < M; v++) sacc[v * VS + base + k * ST] = acc[k][v];
+}
+
+// Right-hand side along axis A for all lines of the space-time element
+// (one thread per line, lines enumerated over (l0, the other spatial
+// indices)), accumulated onto the earlier axes (A > 0).
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS>
+__device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int ST = ipow(n, A);
+  for (int L = threadIdx.x; L < NST / n; L += BS) {
+    const int l0 = L / NF, r = L - l0 * NF;
+    const int base = l0 * ND + r % ST + (r / ST) * ST * n;
+    line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0)>(P, sq, sacc, base, irho, lam, mu);
+  }
+}
+
+// The right-hand side of a time-constant state w (compact [M][ND]) on one
+// time slice, all axes at once: wavefront W takes the lines of axis W (and
+// W + BS/64, ...), one lane per line (n^(D-1) <= 64 lines per axis), and
+// stores that axis's contribution in part[A][M][ND]; the sum over A is left
+// to the consumer.
+template <int D, int N, class PDE, typename T, bool kRoundBF, int BS>
+__device__ __forceinline__ void rhs_slice(PArg &P, const T *w, T *part, T irho, T lam, T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
+  static_assert(NF <= 64, "one wavefront per axis");
+  const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
+  for (int A = wave; A < D; A += BS / 64) {
+    if (L < NF) {
+      if (A == 0) {
+        line_rhs<D, N, PDE, 0, T, T, kRoundBF, ND, false>(P, w, part, L * n, irho, lam, mu);
+      } else if (A == 1) {
+        if constexpr (D > 1)
+          line_rhs<D, N, PDE, 1, T, T, kRoundBF, ND, false>(P, w, part + M * ND, L % n + (L / n) * n * n, irho,
+                                                            lam, mu);
+      } else {
+        if constexpr (D > 2)
+          line_rhs<D, N, PDE, 2, T, T, kRoundBF, ND, false>(P, w, part + 2 * M * ND, L, irho, lam, mu);
+      }
+    }
   }
 }
 
@@ -330,9 +368,8 @@ __device__ __forceinline__ double opTrow<double>(PArg &P, int l) { return cload(
 template <>
 __device__ __forceinline__ float opTrow<float>(PArg &P, int l) { return cload(&P.sw->Trowf[l]); }
 
-template <int D, int N, class PDE, typename T, typename TO, int BS, bool kConst>
-__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout,
-                                           const double *ureg, T dt) {
+template <int D, int N, class PDE, typename T, typename TO, int BS>
+__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout, const double *ureg, T dt) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NU = TimeItems<D, N, M, BS>::value;
@@ -342,47 +379,139 @@ __device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout,
     if (i < M * ND) {
       const int v = i / ND, k = i - v * ND;
       const T u0 = (T)ureg[r];
-      if constexpr (kConst) {
-        // R is the same at every time node: sum_j T[l][j] R = Trow[l] R
-        // (R stored compactly as [M][ND])
-        const T r0 = sacc[v * ND + k];
+      T rr[n];
 #pragma unroll
-        for (int l = 0; l < n; l++) qout[v * NST + l * ND + k] = (TO)(u0 + dt * (opTrow<T>(P, l) * r0));
-      } else {
-        T rr[n];
+      for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
 #pragma unroll
-        for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
+      for (int l = 0; l < n; l++) {
+        T a = T(0);
 #pragma unroll
-        for (int l = 0; l < n; l++) {
-          T a = T(0);
-#pragma unroll
-          for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
-          qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
-        }
+        for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
+        qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
       }
     }
   }
 }
 
-// One Picard sweep: R(q) over all axes, then the time contraction.  With
-// kConst the iterate is constant in time (the first sweep from q^0 = u), so
-// R is evaluated on one time slice and the time operator reduces to its row
-// sums -- the same values as the full sweep up to rounding.
-template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS,
-          bool kConst = false>
+// Sum of the D per-axis parts of a one-slice right-hand side for the
+// values this thread owns (ureg layout: i = threadIdx.x + r*BS).
+template <int D, int N, class PDE, typename T, int BS>
+__device__ __forceinline__ void gather_parts(const T *part, T (&out)[TimeItems<D, N, PDE::M, BS>::value]) {
+  constexpr int M = PDE::M, ND = Shape<D, N>::ND;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    T a = T(0);
+    if (i < M * ND)
+#pragma unroll
+      for (int A = 0; A < D; A++) a += part[A * M * ND + i];
+    out[r] = a;
+  }
+}
+
+// One Picard sweep: R(q) over all axes, then the time contraction.
+template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS>
 __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu) {
-  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
+  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
   if constexpr (D > 1) {
-    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
   if constexpr (D > 2) {
-    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS, kConst>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
-  time_phase<D, N, PDE, T, TO, BS, kConst>(P, sacc, qout, ureg, dt);
+  time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
+  __syncthreads();
+}
+
+// The first sweep from the time-constant iterate q^0 = u (compact [M][ND]
+// in w): R is the same at every time node, so it is evaluated on one time
+// slice (D per-axis parts in `part`, D M ND values) and the time operator
+// reduces to its row sums -- the same values as a full sweep up to rounding.
+// The sums are taken into registers before any write, so qout may overlap
+// `part`.
+template <int D, int N, class PDE, typename T, typename TO, bool kRoundBF, int BS>
+__device__ __forceinline__ void first_sweep(PArg &P, const T *w, T *part, TO *qout, const double *ureg, T dt,
+                                            T irho, T lam, T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+  rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, w, part, irho, lam, mu);
+  __syncthreads();
+  T r0[NU];
+  gather_parts<D, N, PDE, T, BS>(part, r0);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    if (i < M * ND) {
+      const int v = i / ND, k = i - v * ND;
+      const T u0 = (T)ureg[r];
+#pragma unroll
+      for (int l = 0; l < n; l++) qout[v * NST + l * ND + k] = (TO)(u0 + dt * (opTrow<T>(P, l) * r0[r]));
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T>
+__device__ __forceinline__ T opXi(PArg &P, int l);
+template <>
+__device__ __forceinline__ double opXi<double>(PArg &P, int l) { return cload(&P.sw->xi[l]); }
+template <>
+__device__ __forceinline__ float opXi<float>(PArg &P, int l) { return cload(&P.sw->xif[l]); }
+
+// Initial guess of the Picard iteration (Sec. 2.2), as a Taylor polynomial
+// in t - t^n = xi_l dt evaluated at the time nodes:
+//   guess 1: q0 = u + (t - t^n) k1,                                  k1 = L(u)
+//   guess 2: q0 = u + (t - t^n) k1 + (t - t^n)^2 (k2 - k1) / (2 dt),  k2 = L(u + dt k1).
+// On entry sq holds u in the compact [M][ND] layout, on exit the guess in
+// the space-time layout [M][n][ND]; sk is scratch for D M ND values that
+// does not overlap sq.
+template <int D, int N, class PDE, typename T, bool kRoundBF, int BS>
+__device__ __forceinline__ void initial_guess(PArg &P, T *sq, T *sk, const double *ureg, T dt, T irho, T lam,
+                                              T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+  rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, sq, sk, irho, lam, mu);
+  __syncthreads();
+  T k1[NU], c2[NU];
+  gather_parts<D, N, PDE, T, BS>(sk, k1);
+  const bool third = P.guess == 2;
+  if (third) {
+#pragma unroll
+    for (int r = 0; r < NU; r++) {
+      const int i = threadIdx.x + r * BS;
+      if (i < M * ND) sq[i] = (T)ureg[r] + dt * k1[r];
+    }
+    __syncthreads();
+    rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, sq, sk, irho, lam, mu);
+    __syncthreads();
+    gather_parts<D, N, PDE, T, BS>(sk, c2);
+#pragma unroll
+    for (int r = 0; r < NU; r++) c2[r] = T(0.5) * (c2[r] - k1[r]);
+  } else {
+#pragma unroll
+    for (int r = 0; r < NU; r++) c2[r] = T(0);
+  }
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    if (i < M * ND) {
+      const int v = i / ND, k = i - v * ND;
+      const T u0 = (T)ureg[r];
+#pragma unroll
+      for (int l = 0; l < n; l++) {
+        const T x = opXi<T>(P, l);
+        sq[v * NST + l * ND + k] = u0 + dt * (x * k1[r] + x * x * c2[r]);
+      }
+    }
+  }
   __syncthreads();
 }
 
@@ -791,9 +920,15 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     // reads only its time slice 0
     stage_slice0<D, N, PDE, double, BS>(sq, ureg);
     __syncthreads();
-    // the first sweep starts from the time-constant iterate q^0 = u
-    picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
-    for (int s = 1; s < P.sweeps; s++)
+    int full = P.sweeps;  // sweeps over all time slices
+    if (P.guess == 0) {
+      // the first sweep starts from the time-constant iterate q^0 = u
+      first_sweep<D, N, PDE, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+      full -= 1;
+    } else {
+      initial_guess<D, N, PDE, double, false, BS>(P, sq, sacc, ureg, dt, irho, lam, mu);
+    }
+    for (int s = 0; s < full; s++)
       picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
     predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, ureg, dt, e, qo, irho, lam, mu);
   } else {
@@ -801,22 +936,30 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     float *sq32 = (float *)smem_raw;
     double *sR = (double *)(smem_raw + L::A);
     float *sacc32 = (float *)sR;
-    if (P.sweeps == 1) {
+    if (P.sweeps == 1 && P.guess == 0) {
       // a single sweep is the FP64 one, from q^0 = u itself: region A holds
-      // u and the right-hand side (compact [M][ND] each, 2*M*ND doubles fit),
-      // the sweep's iterate lands in region R
-      static_assert(2 * M * ND * 8 <= L::A, "region A holds two compact slices");
+      // u (compact), region R the per-axis parts and then the iterate
+      static_assert(D * M * ND * 8 <= L::R, "region R holds the per-axis parts");
       double *su = (double *)smem_raw;
       stage_slice0<D, N, PDE, double, BS>(su, ureg);
       __syncthreads();
-      picard_sweep<D, N, PDE, double, double, double, false, BS, true>(P, su, su + M * ND, sR, ureg, dt, irho,
-                                                                       lam, mu);
+      first_sweep<D, N, PDE, double, double, false, BS>(P, su, sR, sR, ureg, dt, irho, lam, mu);
       predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
       return;
     }
     stage_slice0<D, N, PDE, float, BS>(sq32, ureg);
     __syncthreads();
     const float dtf = (float)dt;
+    // FP32 sweeps over all time slices before the FP64 one
+    int full32 = P.sweeps - 1;
+    if (P.guess == 0) {
+      // first sweep from the time-constant iterate q^0 = u
+      first_sweep<D, N, PDE, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho, (float)lam,
+                                                    (float)mu);
+      full32 -= 1;
+    } else {
+      initial_guess<D, N, PDE, float, kBF, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu);
+    }
     if constexpr (PREC == kFP32 && kMfma) {
       // per-lane A operands: operator rows k = 4c + (lane & 3)
       float Db[2][n], Tb[2][n];
@@ -829,16 +972,10 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
           Db[c][j] = k < n ? cload(&P.sw->Df[k * kMaxN + j]) : 0.f;
           Tb[c][j] = k < n ? cload(&P.sw->Tf[k * kMaxN + j]) : 0.f;
         }
-      // first sweep from the time-constant iterate q^0 = u
-      picard_sweep<D, N, PDE, float, float, float, false, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
-                                                                    (float)irho, (float)lam, (float)mu);
-      for (int s = 1; s + 1 < P.sweeps; s++)
+      for (int s = 0; s < full32; s++)
         picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
     } else {
-      // first sweep from the time-constant iterate q^0 = u
-      picard_sweep<D, N, PDE, float, float, float, kBF, BS, true>(P, sq32, sacc32, sq32, ureg, dtf,
-                                                                  (float)irho, (float)lam, (float)mu);
-      for (int s = 1; s + 1 < P.sweeps; s++)
+      for (int s = 0; s < full32; s++)
         picard_sweep<D, N, PDE, float, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho,
                                                           (float)lam, (float)mu);
     }

@@ -154,6 +154,7 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
   if (d.prec != ADER_FP64 && d.prec != ADER_FP32 && d.prec != ADER_BF16)
     return fail(c, ADER_ERR_INVALID, w + "unknown precision");
   if (d.picard_iters < 0) return fail(c, ADER_ERR_INVALID, w + "picard_iters must be >= 0");
+  if (d.guess < 0 || d.guess > 2) return fail(c, ADER_ERR_INVALID, w + "guess must be 0, 1 or 2");
   if (!(d.cfl > 0.0) || d.cfl > 1.0) return fail(c, ADER_ERR_INVALID, w + "cfl must be in (0, 1]");
   return ADER_OK;
 }
@@ -280,6 +281,7 @@ PredArgs pred_args(const ProbState &s, int p) {
     for (int sd = 0; sd < 2; sd++) a.trace[ax][sd] = s.trace[ax][sd];
   a.acc_glob = s.acc;
   a.sweeps = s.sweeps;
+  a.guess = s.desc.guess;
   return a;
 }
 
@@ -302,7 +304,7 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
   const int64_t Et = s.E < 32768 ? s.E : 32768;
   const std::string key = std::to_string(s.D) + "/" + std::to_string(s.N) + "/" +
                           std::to_string(s.desc.pde) + "/" + std::to_string(s.desc.prec) + "/" +
-                          std::to_string(Et) + "/" + std::to_string(s.sweeps);
+                          std::to_string(Et) + "/" + std::to_string(s.sweeps) + "/" + std::to_string(s.desc.guess);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -667,7 +669,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       return bail(ADER_ERR_INVALID);
     }
     s.coef = d.cfl * stability_alpha(s.N);
-    s.sweeps = d.picard_iters > 0 ? d.picard_iters : s.N + 1;
+    s.sweeps = d.picard_iters > 0 ? d.picard_iters : (s.N + 1 - d.guess > 1 ? s.N + 1 - d.guess : 1);
     s.u_off = uoff;
     s.u_cnt = s.E * s.m * s.nd;
     s.q_off = qoff;
@@ -688,6 +690,8 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     for (int k = 0; k < kMaxN; k++) {
       s.sw.Trow[k] = s.ops.Trow[k];
       s.sw.Trowf[k] = (float)s.ops.Trow[k];
+      s.sw.xi[k] = s.ops.xi[k];
+      s.sw.xif[k] = (float)s.ops.xi[k];
     }
     const size_t acc_bytes = (size_t)s.m * s.ks.ACC * sizeof(double);
     s.trace_elt = d.prec == ADER_FP64 ? sizeof(double) : sizeof(float);

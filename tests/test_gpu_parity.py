@@ -356,3 +356,28 @@ def test_picard_counts(A, orc, prec, picard):
     ug, _ = gpu_run(A, prob, u0, 3)
     uo, _ = orc_run(orc, mk("fp64"), u0, 3)
     check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{prec} P={picard}")
+
+
+GUESS_CASES = [
+    ("euler3d_N4", lambda pr, g: I.Problem(dim=3, N=4, nel=(3, 4, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr, guess=g),
+     lambda p: I.density_wave(p), 4),
+    ("euler3d_N2", lambda pr, g: I.Problem(dim=3, N=2, nel=(4, 3, 3), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr, guess=g),
+     lambda p: I.fourier_modes(p), 4),
+    ("vortex2d_N3", lambda pr, g: I.vortex_problem(nel=8, N=3, prec=pr, guess=g), I.isentropic_vortex, 4),
+    ("elastic_N3", lambda pr, g: I.elastic_problem(nel=3, N=3, prec=pr, guess=g),
+     lambda p: I.stress_pulse(p, width=0.25), 4),
+]
+
+
+@pytest.mark.parametrize("guess", [1, 2])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,mk,init,steps", GUESS_CASES, ids=[c[0] for c in GUESS_CASES])
+def test_initial_guesses(A, orc, name, mk, init, steps, prec, guess):
+    """MUSCL-Hancock type (1) and third-order Taylor type (2) initial guesses
+    with their default sweep counts, against the oracle's."""
+    prob = mk(prec, guess)
+    u0 = init(prob)
+    say(f"[guess] {name} {prec} guess={guess}")
+    ug, _ = gpu_run(A, prob, u0, steps)
+    uo, _ = orc_run(orc, mk("fp64", guess), u0, steps)
+    check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec} guess={guess}")
