@@ -69,6 +69,7 @@ def lib():
         L.orc_corrector.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP]
         L.orc_step.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP]
         L.orc_totals.argtypes = [C.POINTER(_Problem), _DP, _DP]
+        L.orc_detect.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_void_p]
         _lib = L
     return _lib
 
@@ -153,6 +154,16 @@ def predictor(prob, u: np.ndarray, dt: float) -> np.ndarray:
     q = np.zeros((b.E, b.m, b.n, b.nd))
     assert lib().orc_predictor(b.ref, _ptr(u), float(dt), _ptr(q)) == 0
     return q
+
+
+def detect(prob, u_old: np.ndarray, u_new: np.ndarray) -> np.ndarray:
+    """Troubled-element flags [E] (bit 1 NaN/Inf, 2 positivity, 4 relaxed DMP)."""
+    b = _Bound(prob)
+    u_old = np.ascontiguousarray(u_old, dtype=np.float64)
+    u_new = np.ascontiguousarray(u_new, dtype=np.float64)
+    flags = np.zeros(b.E, dtype=np.int32)
+    assert lib().orc_detect(b.ref, _ptr(u_old), _ptr(u_new), flags.ctypes.data_as(C.c_void_p)) == 0
+    return flags
 
 
 def initial_guess(prob, u: np.ndarray, dt: float) -> np.ndarray:

@@ -680,6 +680,62 @@ int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *d
 
 /* Domain integral of each variable: sum_e |Omega_e| sum_k (prod_a w_ka) u,
  * accumulated with Neumaier's compensated summation in element order. */
+/* ------------------------------------------------------------------ */
+/* A posteriori detection (Sec. 2.3, detection criteria of the limiter) */
+/* ------------------------------------------------------------------ */
+
+int orc_detect(const orc_problem *p, const double *u_old, const double *u_new, int *flags) {
+  setup_t s;
+  if (setup(p, &s)) return -1;
+  const int m = s.m, nd = s.nd, d = s.d;
+#pragma omp parallel for schedule(static)
+  for (int e = 0; e < s.E; e++) {
+    const double *un = u_new + (size_t)e * m * nd;
+    int f = 0;
+    for (int i = 0; i < m * nd; i++)
+      if (!isfinite(un[i])) f |= 1;
+    if (p->pde == ORC_EULER)
+      for (int k = 0; k < nd; k++) {
+        double qv[MAXM];
+        for (int v = 0; v < m; v++) qv[v] = un[v * nd + k];
+        if (!(qv[0] > 0.0) || !(euler_pressure(d, p->gamma, qv) > 0.0)) f |= 2;
+      }
+    /* the vertex neighbourhood: offsets in {-1,0,1}^d */
+    int idx[3] = {0, 0, 0}, rem = e;
+    for (int b = 0; b < d; b++) {
+      idx[b] = rem % p->nel[b];
+      rem /= p->nel[b];
+    }
+    int nb = 1;
+    for (int b = 0; b < d; b++) nb *= 3;
+    for (int v = 0; v < m; v++) {
+      double lo = INFINITY, hi = -INFINITY;
+      for (int o = 0; o < nb; o++) {
+        int r = o, j[3] = {0, 0, 0};
+        for (int b = 0; b < d; b++) {
+          j[b] = (idx[b] + (r % 3) - 1 + p->nel[b]) % p->nel[b];
+          r /= 3;
+        }
+        int en = 0;
+        for (int b = d - 1; b >= 0; b--) en = en * p->nel[b] + j[b];
+        const double *uo = u_old + ((size_t)en * m + v) * nd;
+        for (int k = 0; k < nd; k++) {
+          lo = fmin(lo, uo[k]);
+          hi = fmax(hi, uo[k]);
+        }
+      }
+      const double delta = fmax(1e-4, 1e-3 * (hi - lo));
+      const double lo_r = lo - delta, hi_r = hi + delta;
+      for (int k = 0; k < nd; k++) {
+        const double x = un[v * nd + k];
+        if (x < lo_r || x > hi_r) f |= 4;
+      }
+    }
+    flags[e] = f;
+  }
+  return 0;
+}
+
 int orc_totals(const orc_problem *p, const double *u, double *sums) {
   setup_t s;
   if (setup(p, &s)) return -1;

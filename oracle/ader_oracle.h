@@ -58,6 +58,20 @@ typedef struct {
 /* Picard sweeps used for a problem: picard, or max(1, N+1-guess). */
 int orc_sweeps(const orc_problem *p);
 
+/* A posteriori detection of troubled elements (Sec. 2.3: the checks that
+ * decide which cells the subcell limiter recomputes), on a candidate state
+ * u_new after a step from u_old.  flags[e] (host [E]) is a bit set:
+ *   1  a value of u_new(e) is NaN or infinite;
+ *   2  Euler: rho <= 0 or p <= 0 at a node of u_new(e);
+ *   4  relaxed discrete maximum principle violated: for some variable v a
+ *      nodal value of u_new(e) lies outside [m - delta, M + delta], where m
+ *      and M are the minimum and maximum of the nodal values of u_old over
+ *      e and every element sharing a vertex with it (3^d elements,
+ *      periodic), and delta = max(1e-4, 1e-3 (M - m)).
+ * (Readings: nodal values as the points of the polynomial DMP; the
+ * vertex neighbourhood; the constants 1e-4 and 1e-3.)  Returns 0. */
+int orc_detect(const orc_problem *p, const double *u_old, const double *u_new, int *flags);
+
 /* 1-D basis on [0,1] (Sec. 2.1). */
 int orc_gauss_legendre(int n, double *xi, double *w);
 double orc_lagrange(int n, const double *xi, int k, double x);

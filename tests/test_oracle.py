@@ -439,3 +439,77 @@ def test_last_step_lands_on_t_end(orc):
     prob = I.vortex_problem(nel=4, N=1)
     u, t, steps = orc.run(prob, I.isentropic_vortex(prob), 0.0, 0.637)
     assert t == 0.637 and steps >= 2
+
+
+# ---------------------------------------------- a posteriori detection (Sec. 2.3)
+
+def _detect_case(orc):
+    prob = I.Problem(dim=3, N=2, nel=(4, 3, 3), lo=(0,) * 3, hi=(1,) * 3)
+    u = I.density_wave(prob, noise=0)
+    return prob, u
+
+
+def test_detect_smooth_step_flags_nothing(orc):
+    """A resolved smooth step raises no flag (N = 3 on 4^3: the extremum of
+    the wave moves between nodes by less than the relaxation)."""
+    prob = I.Problem(dim=3, N=3, nel=(4, 4, 4), lo=(0,) * 3, hi=(1,) * 3)
+    u = I.density_wave(prob, noise=0)
+    un, _, _ = orc.step(prob, u, 0.0, 1e9)
+    assert not orc.detect(prob, u, un).any()
+
+
+def test_detect_flags_a_jump(orc):
+    """A density jump (Sod-like slab, p uniform) makes the unlimited scheme
+    over- and undershoot next to the discontinuities: those elements, and
+    only elements within one layer of a jump, are flagged by the DMP."""
+    prob = I.Problem(dim=3, N=3, nel=(8, 2, 2), lo=(0,) * 3, hi=(1,) * 3)
+    X = I.grid(prob)
+    rho = np.where((X[0] > 0.25) & (X[0] < 0.75), 1.0, 0.125)
+    z = np.zeros_like(rho)
+    u = I.pack(prob, I.euler_state(prob, rho, [z, z, z], np.ones_like(rho)))
+    un, _, _ = orc.step(prob, u, 0.0, 1e9)
+    f = orc.detect(prob, u, un)
+    ix = np.arange(prob.E) % 8
+    assert np.all((f & 4)[np.isin(ix, (1, 2, 5, 6))] == 4), f
+    assert not f[np.isin(ix, (0, 3, 4, 7))].any(), f
+
+
+def test_detect_criteria(orc):
+    """Each criterion on its own, on a copy of u (a candidate equal to the
+    old state passes): NaN -> 1; negative density -> 2 (+4: it also leaves
+    the density bounds); a value just inside / just outside the relaxed
+    bound of the neighbourhood -> 0 / 4."""
+    prob, u = _detect_case(orc)
+    assert not orc.detect(prob, u, u).any()
+    e = 7
+    bad = u.copy(); bad[e, 2, 5] = np.nan
+    f = orc.detect(prob, u, bad)
+    assert f[e] & 1 and not f[e] & 4 and np.count_nonzero(f) == 1   # (a NaN pressure also fails bit 2)
+    bad = u.copy(); bad[e, 0, 3] = -0.5
+    f = orc.detect(prob, u, bad)
+    assert f[e] == 2 | 4 and np.count_nonzero(f) == 1
+    # the bound is the max over the 27-element vertex neighbourhood of e
+    idx = [e % 4, (e // 4) % 3, e // 12]
+    neigh = [((idx[0] + a) % 4) + 4 * (((idx[1] + b) % 3) + 3 * ((idx[2] + c) % 3))
+             for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+    v = 4
+    lo, hi = u[neigh, v].min(), u[neigh, v].max()
+    delta = max(1e-4, 1e-3 * (hi - lo))
+    ok = u.copy(); ok[e, v, 0] = hi + 0.999 * delta
+    assert not orc.detect(prob, u, ok).any()
+    out = u.copy(); out[e, v, 0] = hi + 1.001 * delta
+    f = orc.detect(prob, u, out)
+    assert f[e] == 4 and np.count_nonzero(f) == 1
+
+
+def test_detect_uses_corner_neighbours(orc):
+    """A candidate above the element's own maximum but below the maximum of
+    a corner (vertex-only) neighbour is not flagged."""
+    prob, u = _detect_case(orc)
+    u = u.copy()
+    e, corner = 0, 1 + 4 * (1 + 3 * 1)      # (0,0,0) and (1,1,1)
+    u[corner, 0, :] += 0.5                     # raise the corner neighbour's density
+    cand = u.copy()
+    cand[e, 0, 0] = u[e, 0].max() + 0.25       # above e's own max, below the corner's
+    f = orc.detect(prob, u, cand)
+    assert f[e] == 0
