@@ -149,6 +149,26 @@ ader_status ader_step(ader_ctx *ctx, double *u, const double *t_end_host);
  * between calls costs one synchronous copy. */
 ader_status ader_run(ader_ctx *ctx, double *u, const double *t_end_host, int32_t nsteps);
 
+/* A posteriori detection of troubled elements (Sec. 2.3: the criteria that
+ * mark cells for the subcell limiter; the limiter itself is not part of
+ * this library).  With enable != 0 every following ader_step / ader_run
+ * step also records, per element, the extremes of each variable of the
+ * state it starts from (in the time-step kernel) and, after the update,
+ * checks the new state: bit 1 a value is NaN or infinite; bit 2 (Euler)
+ * rho <= 0 or p <= 0 at a node; bit 4 the relaxed discrete maximum
+ * principle fails: for some variable a nodal value lies outside
+ * [m - delta, M + delta], m and M the extremes of the previous state over
+ * the element and the 3^d elements sharing a vertex with it (periodic),
+ * delta = max(1e-4, 1e-3 (M - m)).  Allocates 4 bytes per element and
+ * 16 m bytes per element at the first enable; switching drops a captured
+ * ader_run graph.  The detection time is counted in the update stage of
+ * ader_stage_times. */
+ader_status ader_set_detection(ader_ctx *ctx, int32_t enable);
+/* Flags of the last detected step, host int32 [sum over problems of E],
+ * problems in order, elements e = ix + nx (iy + ny iz) within a problem;
+ * synchronises.  ADER_ERR_INVALID if detection was never enabled. */
+ader_status ader_detect_flags(ader_ctx *ctx, int32_t *flags_host);
+
 /* Current simulation time of every problem (host [nprob]); synchronises and
  * reports a latched ADER_ERR_NONFINITE. */
 ader_status ader_time(ader_ctx *ctx, double *t_host);

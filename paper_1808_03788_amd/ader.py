@@ -27,7 +27,7 @@ EXPORTS = [
     "ader_predictor", "ader_qhat_layout", "ader_corrector", "ader_step", "ader_time",
     "ader_set_time", "ader_last_dt", "ader_totals", "ader_last_error",
     "ader_stability_alpha", "ader_basis", "ader_version", "ader_profile", "ader_stage_times",
-    "ader_describe", "ader_run",
+    "ader_describe", "ader_run", "ader_set_detection", "ader_detect_flags",
 ]
 
 
@@ -70,6 +70,8 @@ def lib():
         L.ader_corrector.argtypes = [_VP, _VP, _VP]
         L.ader_step.argtypes = [_VP, _VP, _DP]
         L.ader_run.argtypes = [_VP, _VP, _DP, C.c_int32]
+        L.ader_set_detection.argtypes = [_VP, C.c_int32]
+        L.ader_detect_flags.argtypes = [_VP, _VP]
         L.ader_time.argtypes = [_VP, _DP]
         L.ader_set_time.argtypes = [_VP, _DP]
         L.ader_last_dt.argtypes = [_VP, _DP]
@@ -207,6 +209,16 @@ def ader_step(ctx: int, u, t_end: Sequence[float]):
 def ader_run(ctx: int, u, t_end: Sequence[float], nsteps: int):
     te = np.ascontiguousarray(t_end, dtype=np.float64)
     _check(lib().ader_run(_VP(ctx), _VP(_ptr(u)), te.ctypes.data_as(_DP), int(nsteps)), ctx)
+
+
+def ader_set_detection(ctx: int, enable: bool):
+    _check(lib().ader_set_detection(_VP(ctx), 1 if enable else 0), ctx)
+
+
+def ader_detect_flags(ctx: int, total_elements: int) -> np.ndarray:
+    out = np.zeros(total_elements, dtype=np.int32)
+    _check(lib().ader_detect_flags(_VP(ctx), out.ctypes.data_as(_VP)), ctx)
+    return out
 
 
 def ader_time(ctx: int, nprob: int) -> np.ndarray:
@@ -347,6 +359,18 @@ class Context:
         if np.isscalar(t_end):
             t_end = [t_end] * self.nprob
         ader_run(self.ctx, u, t_end, nsteps)
+
+    def set_detection(self, enable=True):
+        ader_set_detection(self.ctx, enable)
+
+    def detect_flags(self):
+        """Troubled-element flags of the last step, one int32 array [E] per problem."""
+        flat = ader_detect_flags(self.ctx, sum(p.E for p in self.problems))
+        out, off = [], 0
+        for p in self.problems:
+            out.append(flat[off:off + p.E].copy())
+            off += p.E
+        return out
 
     def time(self):
         return ader_time(self.ctx, self.nprob)

@@ -1206,6 +1206,7 @@ struct CflArgs {
   int64_t u_off;                  // offset of the problem's u in the state buffer
   const double *mat;
   int pidx;                       // problem index: smax[pidx] collects its maximum
+  double *summ;                   // optional [E][M][2]: min and max of every variable per element
 };
 
 // Per-element wave speed S_e = sum_A (max_k |lambda_A(u_k)|) / h_A and its
@@ -1225,6 +1226,12 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
   for (int ix = wave; ix < nx; ix += kBlock / 64) {
     const int64_t e = row * nx + ix;
     double lm[3] = {0.0, 0.0, 0.0};
+    double vmin[M], vmax[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      vmin[v] = INFINITY;
+      vmax[v] = -INFINITY;
+    }
     const double *ue = u + C.u_off + e * (int64_t)(M * ND);
     for (int k = lane; k < ND; k += 64) {
       double q[M];
@@ -1232,6 +1239,8 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
       for (int v = 0; v < M; v++) {
         q[v] = ue[v * ND + k];
         if (!isfinite(q[v])) bad = 1;
+        vmin[v] = fmin(vmin[v], q[v]);
+        vmax[v] = fmax(vmax[v], q[v]);
       }
       if constexpr (!PDE::kElastic) {
         const double ir = 1.0 / q[0];
@@ -1262,6 +1271,19 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
       se += lm[A] / C.h[A];
     }
     smax = fmax(smax, se);
+    if (C.summ) {  // per-element bounds for the detection after the step
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        for (int off = 32; off > 0; off >>= 1) {
+          vmin[v] = fmin(vmin[v], __shfl_xor(vmin[v], off, 64));
+          vmax[v] = fmax(vmax[v], __shfl_xor(vmax[v], off, 64));
+        }
+        if (lane == 0) {
+          C.summ[(e * M + v) * 2] = vmin[v];
+          C.summ[(e * M + v) * 2 + 1] = vmax[v];
+        }
+      }
+    }
   }
   if (bad) atomicOr(bad_any, 1);
   if (lane == 0) red[wave] = smax;
@@ -1288,6 +1310,82 @@ __global__ void __launch_bounds__(kBlock) k_cfl(const CflArgs *args, const Batch
     const int p = tile_problem(b, tile);
     const CflArgs C = cload(&args[p]);
     cfl_row<D, N, PDE>(C, tile - cload(&b.start[p]), u, smax_bits, err, red, &bad_any);
+  }
+}
+
+// ------------------------------------------------------------ detection
+
+struct DetArgs {
+  Geom g;
+  int64_t u_off;        // offset of the problem's u in the state buffer
+  const double *summ;   // [E][M][2] min/max per element of the state before the step
+  int *flags;           // [E] troubled-element bits of the problem
+};
+
+// A posteriori detection (Sec. 2.3) on the state u after a step: bit 1 a
+// value is NaN or infinite, bit 2 (Euler) rho <= 0 or p <= 0 at a node,
+// bit 4 the relaxed discrete maximum principle fails for some variable: a
+// nodal value outside [m - delta, M + delta], with m, M the extremes of the
+// previous state over the element and the 3^D elements sharing a vertex
+// with it (periodic) and delta = max(1e-4, 1e-3 (M - m)).  A tile is one
+// x-row (tile = iy + ny iz), one wavefront per element.
+template <int D, int N, class PDE>
+__device__ __forceinline__ void detect_row(const DetArgs &A, int64_t row, const double *u) {
+  using S = Shape<D, N>;
+  constexpr int M = PDE::M, ND = S::ND;
+  constexpr int NB = ipow(3, D);
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int nx = A.g.nel[0], ny = A.g.nel[1], nz = A.g.nel[2];
+  const int iy = (int)(row % ny), iz = (int)(row / ny);
+  for (int ix = wave; ix < nx; ix += kBlock / 64) {
+    const int64_t e = row * nx + ix;
+    const double *ue = u + A.u_off + e * (int64_t)(M * ND);
+    int f = 0;
+    for (int k = lane; k < ND; k += 64) {
+      double q[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        q[v] = ue[v * ND + k];
+        if (!isfinite(q[v])) f |= 1;
+      }
+      if constexpr (!PDE::kElastic)
+        if (!(q[0] > 0.0) || !(euler_pressure<D>(q, A.g.gamma) > 0.0)) f |= 2;
+    }
+    // neighbour of lane j: offsets (j % 3 - 1, j / 3 % 3 - 1, j / 9 - 1)
+    int64_t en = e;
+    if (lane < NB) {
+      const int jx = (ix + lane % 3 - 1 + nx) % nx;
+      const int jy = D > 1 ? (iy + lane / 3 % 3 - 1 + ny) % ny : iy;
+      const int jz = D > 2 ? (iz + lane / 9 - 1 + nz) % nz : iz;
+      en = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
+    }
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      double lo = lane < NB ? A.summ[(en * M + v) * 2] : INFINITY;
+      double hi = lane < NB ? A.summ[(en * M + v) * 2 + 1] : -INFINITY;
+      for (int off = 32; off > 0; off >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, off, 64));
+        hi = fmax(hi, __shfl_xor(hi, off, 64));
+      }
+      const double delta = fmax(1e-4, 1e-3 * (hi - lo));
+      const double lo_r = lo - delta, hi_r = hi + delta;
+      for (int k = lane; k < ND; k += 64) {
+        const double x = ue[v * ND + k];
+        if (x < lo_r || x > hi_r) f |= 4;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off, 64);
+    if (lane == 0) A.flags[e] = f;
+  }
+}
+
+template <int D, int N, class PDE>
+__global__ void __launch_bounds__(kBlock) k_detect(const DetArgs *args, const Batch b, const double *u) {
+  const int64_t total = cload(&b.start[b.np]);
+  for (int64_t tile = blockIdx.x; tile < total; tile += gridDim.x) {
+    const int p = tile_problem(b, tile);
+    const DetArgs A = cload(&args[p]);
+    detect_row<D, N, PDE>(A, tile - cload(&b.start[p]), u);
   }
 }
 

@@ -41,6 +41,8 @@ struct ProbState {
   OpsSweep *sw_dev = nullptr;  // device copy read by the predictor
   Ops *ops_dev = nullptr;   // device copy of the tables (outputs, faces, update read them by pointer)
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
+  double *summ = nullptr;           // detection: [E][m][2] extremes of the state before a step
+  int64_t e_off = 0;                // offset of the problem's elements in the flag array
   void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};  // trace type
 };
@@ -56,8 +58,9 @@ struct KClass {
   double tune_ms = 0.0;
   int D = 0;
   const void *face[3] = {nullptr, nullptr, nullptr};
-  const void *update = nullptr, *cfl = nullptr;
+  const void *update = nullptr, *cfl = nullptr, *detect = nullptr;
   PredArgs *pargs = nullptr;               // device [np]
+  DetArgs *dargs = nullptr;                // device [np], once detection is enabled
   FaceArgs *fargs[3] = {nullptr, nullptr, nullptr};
   UpdArgs *uargs = nullptr;
   CflArgs *cargs = nullptr;
@@ -83,6 +86,9 @@ struct ader_ctx {
   std::vector<KClass> K;
   double *dt = nullptr, *t = nullptr, *tnext = nullptr;  // device [nprob]
   double *coef = nullptr, *tend = nullptr;               // device [nprob]
+  bool detect = false;                                   // a posteriori detection after each step
+  int *flags = nullptr;                                  // device [total elements]
+  int64_t total_e = 0;
   std::vector<double> tend_host;                         // values held by tend
   unsigned long long *smax = nullptr;                      // device [nprob]
   int *err = nullptr;                                      // device [1]
@@ -429,6 +435,7 @@ ader_status build_class(ader_ctx *c, KClass &k) {
     cf.u_off = s.u_off;
     cf.mat = s.mat;
     cf.pidx = p;
+    cf.summ = c->detect ? s.summ : nullptr;
     ps[i + 1] = ps[i] + s.E;
     cs[i + 1] = cs[i] + rows;
     for (int r = 0; r < rows; r++) {
@@ -544,6 +551,39 @@ ader_status check_flag(ader_ctx *c) {
   return ADER_OK;
 }
 
+// Detection records of a class, and the time-step records with or without
+// the per-element extremes (re-uploaded when detection is switched).
+ader_status refresh_detection(ader_ctx *c, KClass &k) {
+  const int np = (int)k.probs.size();
+  std::vector<CflArgs> ca(np);
+  HIP_OR_FAIL(c, hipMemcpy(ca.data(), k.cargs, np * sizeof(CflArgs), hipMemcpyDeviceToHost));
+  for (int i = 0; i < np; i++) ca[i].summ = c->detect ? c->P[k.probs[i]].summ : nullptr;
+  HIP_OR_FAIL(c, hipMemcpy(k.cargs, ca.data(), np * sizeof(CflArgs), hipMemcpyHostToDevice));
+  if (c->detect && !k.dargs) {
+    std::vector<DetArgs> da(np);
+    for (int i = 0; i < np; i++) {
+      const ProbState &s = c->P[k.probs[i]];
+      da[i].g = s.g;
+      da[i].u_off = s.u_off;
+      da[i].summ = s.summ;
+      da[i].flags = c->flags + s.e_off;
+    }
+    ader_status st = upload(c, (void **)&k.dargs, da.data(), np * sizeof(DetArgs));
+    if (st) return st;
+  }
+  return ADER_OK;
+}
+
+ader_status run_detect(ader_ctx *c, const double *u) {
+  for (KClass &k : c->K) {
+    Batch b{k.cstart, (int)k.probs.size()};
+    void *args[] = {&k.dargs, &b, &u};
+    ader_status st = launch(c, k.detect, k.ctot, k.cgrid, kBlock, 0, args);
+    if (st) return st;
+  }
+  return ADER_OK;
+}
+
 // Make the device t_end values equal to t_end_host (a synchronous copy,
 // only when they change).
 ader_status set_tend(ader_ctx *c, const double *t_end_host) {
@@ -570,6 +610,7 @@ ader_status step_launches(ader_ctx *c, double *u, bool marks) {
   if ((m && (st = mark(c))) || (st = run_predictor(c, u, nullptr, nullptr))) return st;
   if ((m && (st = mark(c))) || (st = run_faces(c))) return st;
   if ((m && (st = mark(c))) || (st = run_update(c, u, nullptr))) return st;
+  if (c->detect && (st = run_detect(c, u))) return st;  // timed with the update stage
   if (m && (st = mark(c))) return st;
   const int np = (int)c->P.size();
   hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->t, c->tnext, np);
@@ -674,6 +715,8 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     s.u_cnt = s.E * s.m * s.nd;
     s.q_off = qoff;
     s.q_cnt = s.E * s.m * s.nst;
+    s.e_off = c->total_e;
+    c->total_e += s.E;
     uoff += s.u_cnt;
     qoff += s.q_cnt;
     moff += s.m;
@@ -796,6 +839,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       for (int ax = 0; ax < 3; ax++) kc.face[ax] = f64 ? s.ks.face64[ax] : s.ks.face32[ax];
       kc.update = f64 ? s.ks.update64 : s.ks.update32;
       kc.cfl = s.ks.cfl;
+      kc.detect = s.ks.detect;
       c->K.push_back(kc);
     }
     s.cls = k;
@@ -950,6 +994,38 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
   HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, c->gstream));
   HIP_OR_FAIL(c, hipEventRecord(c->g_out, c->gstream));
   HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->g_out, 0));
+  return ADER_OK;
+}
+
+ader_status ader_set_detection(ader_ctx *c, int32_t enable) {
+  if (!c) return ADER_ERR_INVALID;
+  const bool on = enable != 0;
+  if (on == c->detect) return ADER_OK;
+  ader_status st;
+  if (on && !c->flags) {
+    if ((st = dalloc(c, (void **)&c->flags, (size_t)c->total_e * sizeof(int)))) return st;
+    for (ProbState &s : c->P)
+      if ((st = dalloc(c, (void **)&s.summ, (size_t)s.E * s.m * 2 * sizeof(double)))) return st;
+    HIP_OR_FAIL(c, hipMemset(c->flags, 0, (size_t)c->total_e * sizeof(int)));
+  }
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  if (c->gexec) {  // the captured steps no longer match
+    HIP_OR_FAIL(c, hipStreamSynchronize(c->gstream));
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
+  c->detect = on;
+  for (KClass &k : c->K)
+    if ((st = refresh_detection(c, k))) return st;
+  return ADER_OK;
+}
+
+ader_status ader_detect_flags(ader_ctx *c, int32_t *flags_host) {
+  if (!c || !flags_host) return ADER_ERR_INVALID;
+  if (!c->flags) return fail(c, ADER_ERR_INVALID, "detection was never enabled (ader_set_detection)");
+  HIP_OR_FAIL(c, hipMemcpyAsync(flags_host, c->flags, (size_t)c->total_e * sizeof(int), hipMemcpyDeviceToHost,
+                                c->stream));
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   return ADER_OK;
 }
 

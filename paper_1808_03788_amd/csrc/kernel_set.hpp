@@ -25,6 +25,7 @@ struct KernelSet {
   const void *update64 = nullptr;                       // FP64 face integrals
   const void *update32 = nullptr;                       // FP32 face integrals
   const void *cfl = nullptr;
+  const void *detect = nullptr;
   int M = 0, n = 0, ND = 0, NST = 0, NF = 0, ACC = 0;
 };
 
@@ -68,6 +69,7 @@ KernelSet make_kernel_set() {
   k.update64 = (const void *)&k_update<D, N, PDE, double>;
   k.update32 = (const void *)&k_update<D, N, PDE, float>;
   k.cfl = (const void *)&k_cfl<D, N, PDE>;
+  k.detect = (const void *)&k_detect<D, N, PDE>;
   k.M = PDE::M;
   k.n = S::n;
   k.ND = S::ND;
