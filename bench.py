@@ -203,13 +203,15 @@ def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0):
 
 
 def run_path(workload, prec, steps, warmup, I, ader, torch, nel=None, degree=None, picard=0,
-             graph_steps=0, guess=0):
+             graph_steps=0, guess=0, detect=False):
     """Time `steps` steps (or graph replays of `graph_steps` steps each) of
     one precision mode; returns the timings, stage times and the final state
     (device tensor)."""
     probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard, guess)
     note(f"{prec}: {len(probs)} problem(s) generated")
     ctx = ader.Context(probs)
+    if detect:
+        ctx.set_detection(True)
     note(f"{prec}: context created ({ader.ader_describe(ctx.ctx, 0).split()[0]})")
     kernels = ader.ader_describe(ctx.ctx, 0)
     u = ctx.upload(inits)
@@ -303,6 +305,8 @@ def main():
                     help="initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type")
     ap.add_argument("--graph-steps", type=int, default=-1,
                     help="steps per captured-graph replay (0: plain ader_step; -1: 10 for batched, else 0)")
+    ap.add_argument("--detect", action="store_true",
+                    help="a posteriori detection of troubled elements after every step (timed with the update)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device copy (calibrates HBM byte counters)")
@@ -319,7 +323,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gs = args.graph_steps if args.graph_steps >= 0 else (10 if args.workload == "batched" else 0)
     kw = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree, picard=args.picard,
-              graph_steps=gs, guess=args.guess)
+              graph_steps=gs, guess=args.guess, detect=args.detect)
     ref = run_path(args.workload, "fp64", args.steps, args.warmup, I, ader, torch, **kw)
     head = ref if args.prec == "fp64" else run_path(args.workload, args.prec, args.steps, args.warmup, I,
                                                     ader, torch, **kw)
@@ -361,6 +365,7 @@ def main():
         config.update(degree=prob.N, picard_sweeps=sweeps_of(prob), initial_guess=prob.guess)
     else:
         config.update(degrees=sorted({p.N for p in probs}), steps_per_replay=gs)
+    config["detection"] = bool(args.detect)
     line = {
         "metric": METRIC,
         "value": head["value"],
