@@ -38,7 +38,7 @@ class _Problem(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("pde", C.c_int), ("gamma", C.c_double),
         ("material", C.POINTER(C.c_double)),
-        ("picard", C.c_int), ("cfl", C.c_double), ("guess", C.c_int),
+        ("picard", C.c_int), ("cfl", C.c_double), ("guess", C.c_int), ("face_avg", C.c_int),
     ]
 
 
@@ -102,6 +102,7 @@ class _Bound:
         s.picard = int(getattr(prob, "picard", 0) or 0)
         s.cfl = float(getattr(prob, "cfl", 0.9))
         s.guess = int(getattr(prob, "guess", 0) or 0)
+        s.face_avg = int(getattr(prob, "face_avg", 0) or 0)
         self.s = s
         self.n = prob.N + 1
         self.nd = self.n ** prob.dim

@@ -312,6 +312,34 @@ static void dminus(const orc_problem *p, const setup_t *s, const double *qm, con
     D[v] = 0.5 * (Fp[v] + Fm[v]) * sgn + 0.5 * (path[v] - smax * dq[v]);
 }
 
+/* The jump term from time-averaged traces qm, qp and time-averaged
+ * fluxes Fm, Fp (face_avg): the same formula as dminus with the averaged
+ * quantities; the path and s_max come from the averaged states. */
+static void dminus_avg(const orc_problem *p, const setup_t *s, const double *qm, const double *qp,
+                       const double *Fm, const double *Fp, const double *matm, const double *matp,
+                       int a, double sgn, double *D) {
+  int m = s->m;
+  double dq[MAXM], path[MAXM];
+  for (int v = 0; v < m; v++) {
+    dq[v] = qp[v] - qm[v];
+    path[v] = 0.0;
+  }
+  if (p->pde == ORC_ELASTIC) {
+    for (int g = 0; g < 3; g++) {
+      double psi[MAXM], matg[3], grad[3][MAXM], out[MAXM];
+      for (int v = 0; v < m; v++) psi[v] = qm[v] + s->gx[g] * dq[v];
+      for (int c = 0; c < 3; c++) matg[c] = matm[c] + s->gx[g] * (matp[c] - matm[c]);
+      for (int b = 0; b < 3; b++)
+        for (int v = 0; v < m; v++) grad[b][v] = (b == a) ? sgn * dq[v] : 0.0;
+      pde_ncp(p, s, psi, matg, grad, out);
+      for (int v = 0; v < m; v++) path[v] += s->gw[g] * out[v];
+    }
+  }
+  double smax = fmax(pde_speed(p, s, qm, matm, a), pde_speed(p, s, qp, matp, a));
+  for (int v = 0; v < m; v++)
+    D[v] = 0.5 * (Fp[v] + Fm[v]) * sgn + 0.5 * (path[v] - smax * dq[v]);
+}
+
 /* ------------------------------------------------------------------ */
 /* Space-time predictor (Sec. 2.2).                                     */
 /* ------------------------------------------------------------------ */
@@ -554,7 +582,36 @@ static void element_corrector(const orc_problem *p, const setup_t *s, int e, con
       const double *phout = side ? s->F0 : s->F1; /* outside: neighbour's opposite face */
       double sgn = side ? 1.0 : -1.0;
       for (int i = 0; i < m * nd; i++) G[i] = 0.0;
-      for (int k = 0; k < nd; k++) {
+      for (int k = 0; k < nd && p->face_avg; k++) {
+        if (axis_index(s, k, a) != 0) continue;
+        /* time averages of the traces and of their fluxes on this face node */
+        double qi[MAXM], qo[MAXM], Fi[MAXM], Fo[MAXM];
+        for (int v = 0; v < m; v++) qi[v] = qo[v] = Fi[v] = Fo[v] = 0.0;
+        for (int l0 = 0; l0 < n; l0++) {
+          double qin[MAXM], qout[MAXM], f1[MAXM], f2[MAXM];
+          for (int v = 0; v < m; v++) {
+            double si = 0.0, so = 0.0;
+            for (int j = 0; j < n; j++) {
+              si += phin[j] * q[(v * n + l0) * nd + k + j * s->str[a]];
+              so += phout[j] * qn[(v * n + l0) * nd + k + j * s->str[a]];
+            }
+            qin[v] = si;
+            qout[v] = so;
+          }
+          pde_flux(p, s, qin, a, f1);
+          pde_flux(p, s, qout, a, f2);
+          for (int v = 0; v < m; v++) {
+            qi[v] += s->w[l0] * qin[v];
+            qo[v] += s->w[l0] * qout[v];
+            Fi[v] += s->w[l0] * f1[v];
+            Fo[v] += s->w[l0] * f2[v];
+          }
+        }
+        double D[MAXM];
+        dminus_avg(p, s, qi, qo, Fi, Fo, mat, matn, a, sgn, D);
+        for (int v = 0; v < m; v++) G[v * nd + k] = D[v];
+      }
+      for (int k = 0; k < nd && !p->face_avg; k++) {
         if (axis_index(s, k, a) != 0) continue; /* k enumerates the face nodes */
         for (int l0 = 0; l0 < n; l0++) {
           double qin[MAXM], qout[MAXM], D[MAXM];

@@ -53,6 +53,7 @@ typedef struct {
                           q0(t) = u + (t - t^n) k1 + (t - t^n)^2 (k2 - k1) / (2 dt),
                           k1 = L(u), k2 = L(u + dt k1);
                        L = S - div F - B.grad, the collocated right-hand side. */
+  int face_avg;     /* face integrals from time-averaged traces (see orc_corrector) */
 } orc_problem;
 
 /* Picard sweeps used for a problem: picard, or max(1, N+1-guess). */

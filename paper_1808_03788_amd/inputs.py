@@ -40,6 +40,7 @@ class Problem:
     cfl: float = 0.9
     prec: str = "fp64"            # predictor precision: fp64 | fp32 | bf16
     guess: int = 0                # initial guess of the Picard iteration
+    face_avg: int = 0             # face integrals from time-averaged traces
 
     @property
     def n(self) -> int:

@@ -513,3 +513,38 @@ def test_detect_uses_corner_neighbours(orc):
     cand[e, 0, 0] = u[e, 0].max() + 0.25       # above e's own max, below the corner's
     f = orc.detect(prob, u, cand)
     assert f[e] == 0
+
+
+# ---------------------------------------------- face integrals from time averages
+
+def test_face_avg_exact_for_elasticity(orc):
+    """For the elastic system the jump term is linear in the traces with
+    time-independent coefficients, so integrating averaged traces equals the
+    per-time-node integral (to rounding), including at material jumps."""
+    kw = dict(nel=3, N=3)
+    p0 = I.elastic_problem(**kw)
+    p1 = I.elastic_problem(face_avg=1, **kw)
+    u = I.stress_pulse(p0, width=0.2)
+    a, _ = orc.run(p0, u, 0.0, 1e9, max_steps=3)[:2]
+    b, _ = orc.run(p1, u, 0.0, 1e9, max_steps=3)[:2]
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(a).max()
+
+
+def test_face_avg_euler_order_and_conservation(orc):
+    """Euler with averaged traces: only the Rusanov speed changes, so the
+    design order N+1 and conservation are kept, and the result stays close
+    to the per-time-node one on smooth data."""
+    errs = []
+    for nel in (4, 8):
+        prob = I.density_wave_problem(nel=nel, N=3, face_avg=1)
+        u, t, _ = orc.run(prob, I.density_wave(prob, noise=0), 0.0, 0.05)
+        errs.append(I.l2_per_var(prob, u - I.density_wave(prob, t=t, noise=0))[0])
+    assert _order(errs)[0] > 4 - 0.4, errs
+    p0 = I.density_wave_problem(nel=4, N=3)
+    p1 = I.density_wave_problem(nel=4, N=3, face_avg=1)
+    u = I.density_wave(p0)
+    s0 = orc.totals(p0, u)
+    a, _, _ = orc.run(p0, u, 0.0, 1e9, max_steps=3)
+    b, _, _ = orc.run(p1, u, 0.0, 1e9, max_steps=3)
+    assert np.abs(orc.totals(p1, b) - s0).max() <= 1e-13 * np.abs(s0).max()
+    assert 0 < I.rel_l2(p0, b, a) < 1e-5
