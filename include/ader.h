@@ -83,6 +83,14 @@ typedef struct {
                            2 q0 = u + (t-t^n) k1 + (t-t^n)^2 (k2-k1)/(2 dt), k1 = L(u),
                            k2 = L(u + dt k1) (third order); L = S - div F - B.grad.
                            Guesses 1 and 2 are computed in the sweeps' precision. */
+  int32_t face_avg;     /* 0: the jump term at every face node and time node, integrated in
+                           time (eqs. pc.scheme, rusanov); 1: from time-averaged traces,
+                           qbar = sum w_l q(l) and (Euler) Fbar = sum w_l F(q(l)):
+                           G = 1/2 (Fbar+ + Fbar-).n + 1/2 (path - s_max)(qbar+ - qbar-),
+                           s_max from the averaged states.  Exact for elasticity (linear,
+                           time-independent coefficients); for Euler only the Rusanov speed
+                           changes.  Stores 2m (Euler) or m (elasticity) values per face node
+                           and side instead of (N+1) m. */
 } ader_problem;
 
 /* Create a context for `nprob` independent problems (Sec. 2; the problems

@@ -37,7 +37,7 @@ class ader_problem(C.Structure):
         ("lo", C.c_double * 3), ("hi", C.c_double * 3),
         ("pde", C.c_int32), ("gamma", C.c_double), ("material", C.POINTER(C.c_double)),
         ("prec", C.c_int32), ("picard_iters", C.c_int32), ("cfl", C.c_double),
-        ("guess", C.c_int32),
+        ("guess", C.c_int32), ("face_avg", C.c_int32),
     ]
 
 
@@ -149,6 +149,7 @@ def make_problem(prob, keep: list) -> ader_problem:
     s.prec = PREC[getattr(prob, "prec", "fp64")]
     s.picard_iters = int(getattr(prob, "picard", 0) or 0)
     s.guess = int(getattr(prob, "guess", 0) or 0)
+    s.face_avg = int(getattr(prob, "face_avg", 0) or 0)
     s.cfl = float(getattr(prob, "cfl", 0.9))
     return s
 

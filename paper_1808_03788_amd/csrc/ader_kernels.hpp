@@ -183,7 +183,13 @@ struct PredArgs {
   double *acc_glob;     // FP64 accumulator when it does not fit in LDS: [E][M][ACC]
   int sweeps;
   int guess;            // initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type
+  int face_avg;         // traces as time averages (qbar and, for Euler, Fbar_A) instead of per time node
 };
+
+// Values per face node of a time-averaged trace: qbar, and for Euler the
+// time-averaged normal flux Fbar_A (the elastic jump term needs qbar only).
+template <class PDE>
+constexpr int avg_comps() { return PDE::kElastic ? PDE::M : 2 * PDE::M; }
 // Argument records are read in place through the constant address space:
 // every field load is a scalar load, whatever the kernel has written.
 using PArg = const __attribute__((address_space(4))) PredArgs;
@@ -827,6 +833,65 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
   }
 }
 
+// Time-averaged trace of one face node on the face of axis A at side s
+// (x_A = 0 or 1): qbar = sum_l0 w_l0 q_s(l0) and, for Euler, the averaged
+// normal flux Fbar_A = sum_l0 w_l0 F_A(q_s(l0)), with q_s(l0) the
+// boundary-extrapolated state; stored as TT in [avg_comps][NF].
+template <int D, int N, class PDE, int A, typename TT>
+__device__ __forceinline__ void trace_avg_node(PArg &P, const double *sq, int64_t e, int side, int kf) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int ST = ipow(n, A), NC = avg_comps<PDE>();
+  const int base = kf % ST + (kf / ST) * ST * n;
+  const double *phi = side ? P.ops->F1 : P.ops->F0;
+  double qb[M], fb[M];
+#pragma unroll
+  for (int v = 0; v < M; v++) qb[v] = fb[v] = 0.0;
+  for (int l0 = 0; l0 < n; l0++) {
+    double qv[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      double a = 0.0;
+#pragma unroll
+      for (int j = 0; j < n; j++) a += cload(&phi[j]) * sq[v * NST + l0 * ND + base + j * ST];
+      qv[v] = a;
+    }
+    const double wl = cload(&P.ops->w[l0]);
+#pragma unroll
+    for (int v = 0; v < M; v++) qb[v] += wl * qv[v];
+    if constexpr (!PDE::kElastic) {
+      double F[M];
+      euler_flux<D, A, double>(qv, P.g.gamma - 1.0, F);
+#pragma unroll
+      for (int v = 0; v < M; v++) fb[v] += wl * F[v];
+    }
+  }
+  TT *t = (TT *)P.trace[A][side] + e * (int64_t)(NC * NF);
+#pragma unroll
+  for (int v = 0; v < M; v++) t[v * NF + kf] = (TT)qb[v];
+  if constexpr (!PDE::kElastic)
+#pragma unroll
+    for (int v = 0; v < M; v++) t[(M + v) * NF + kf] = (TT)fb[v];
+}
+
+// Averaged traces of all 2D faces: wavefront W takes axis W (and W + BS/64),
+// one lane per (side, face node).
+template <int D, int N, class PDE, typename TT, int BS>
+__device__ __forceinline__ void traces_avg(PArg &P, const double *sq, int64_t e) {
+  constexpr int NF = Shape<D, N>::NF;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int A = wave; A < D; A += BS / 64)
+    for (int it = lane; it < 2 * NF; it += 64) {
+      const int side = it / NF, kf = it - side * NF;
+      if (A == 0) trace_avg_node<D, N, PDE, 0, TT>(P, sq, e, side, kf);
+      else if (A == 1) {
+        if constexpr (D > 1) trace_avg_node<D, N, PDE, 1, TT>(P, sq, e, side, kf);
+      } else {
+        if constexpr (D > 2) trace_avg_node<D, N, PDE, 2, TT>(P, sq, e, side, kf);
+      }
+    }
+}
+
 // Predictor outputs from the final FP64 iterate qf: optional qhat copy, the
 // face traces, the volume terms (scratch of D*M*ND doubles) and
 // u* = u + dt V.
@@ -838,9 +903,13 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   if (qo)
     for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
-  traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
-  if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
-  if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
+  if (P.face_avg) {
+    traces_avg<D, N, PDE, TT, BS>(P, qf, e);
+  } else {
+    traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
+    if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
+    if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
+  }
   double *us = P.ustar + e * (int64_t)(M * ND);
   if constexpr (N == 0) {
     for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
@@ -1124,6 +1193,84 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs *args, const Row
     const FaceArgs F = cload(&args[t.p]);
     face_tile<D, N, PDE, A, TT, GT>(F, t.bx, t.yz & 0xffff, t.yz >> 16, sD);
     __syncthreads();  // the next tile overwrites the LDS
+  }
+}
+
+// Faces per workgroup of the face kernel on averaged traces (one thread per
+// face node).
+__host__ __device__ constexpr int face_avg_per_block(int D, int N) {
+  return kBlock / ipow(N + 1, D - 1) > 0 ? kBlock / ipow(N + 1, D - 1) : 1;
+}
+
+// The jump term of a face node from time-averaged traces (option
+// face_avg): G = 1/2 (Fbar+ + Fbar-) - 1/2 s_max (qbar+ - qbar-) for Euler
+// with s_max from the averaged states; for elasticity the per-time-node
+// term integrated exactly (it is linear in the traces with time-independent
+// coefficients).  One thread per (face, face node); a tile is chunk bx of
+// face_avg_per_block faces of the x-row (iy, iz).
+template <int D, int N, class PDE, int A, typename TT, typename GT>
+__device__ __forceinline__ void face_avg_tile(const FaceArgs &F, int bx, int iy, int iz) {
+  using S = Shape<D, N>;
+  constexpr int M = PDE::M, NF = S::NF, NC = avg_comps<PDE>();
+  constexpr int FPB = face_avg_per_block(D, N);
+  const int nx = F.g.nel[0], ny = F.g.nel[1], nz = F.g.nel[2];
+  for (int it = threadIdx.x; it < FPB * NF; it += kBlock) {
+    const int f = it / NF, kf = it - f * NF;
+    const int ix = bx * FPB + f;
+    if (ix >= nx) continue;
+    const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
+    const int jx = (A == 0) ? (ix + 1 == nx ? 0 : ix + 1) : ix;
+    const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
+    const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
+    const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
+    const TT *tm = (const TT *)F.trace1 + e * (int64_t)(NC * NF) + kf;
+    const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(NC * NF) + kf;
+    double qm[M], qp[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      qm[v] = (double)tm[v * NF];
+      qp[v] = (double)tp[v * NF];
+    }
+    GT *gl = (GT *)F.GL + e * (int64_t)(M * NF) + kf;
+    if constexpr (!PDE::kElastic) {
+      const double gamma = F.g.gamma;
+      const double smax = fmax(euler_speed<D, A>(qm, gamma), euler_speed<D, A>(qp, gamma));
+#pragma unroll
+      for (int v = 0; v < M; v++)
+        gl[v * NF] = (GT)(0.5 * ((double)tp[(M + v) * NF] + (double)tm[(M + v) * NF]) - 0.5 * smax * (qp[v] - qm[v]));
+    } else {
+      const double rL = F.mat[3 * e], lL = F.mat[3 * e + 1], mL = F.mat[3 * e + 2];
+      const double rR = F.mat[3 * eR], lR = F.mat[3 * eR + 1], mR = F.mat[3 * eR + 2];
+      const double gs[3] = {0.5 - 0.1 * sqrt(15.0), 0.5, 0.5 + 0.1 * sqrt(15.0)};
+      const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+      double irho = 0.0, lam = 0.0, mu = 0.0;
+#pragma unroll
+      for (int g = 0; g < 3; g++) {
+        irho += gw[g] / (rL + gs[g] * (rR - rL));
+        lam += gw[g] * (lL + gs[g] * (lR - lL));
+        mu += gw[g] * (mL + gs[g] * (mR - mL));
+      }
+      const double smax = fmax(sqrt((lL + 2.0 * mL) / rL), sqrt((lR + 2.0 * mR) / rR));
+      double dq[M], bd[M];
+#pragma unroll
+      for (int v = 0; v < M; v++) dq[v] = qp[v] - qm[v];
+      elastic_bg<A, double>(dq, irho, lam, mu, bd);
+      GT *gr = (GT *)F.GR + e * (int64_t)(M * NF) + kf;
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        gl[v * NF] = (GT)(0.5 * (bd[v] - smax * dq[v]));
+        gr[v * NF] = (GT)(0.5 * (bd[v] + smax * dq[v]));
+      }
+    }
+  }
+}
+
+template <int D, int N, class PDE, int A, typename TT, typename GT>
+__global__ void __launch_bounds__(kBlock) k_face_avg(const FaceArgs *args, const RowTile *tiles, int64_t ntiles) {
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const RowTile t = cload(&tiles[tile]);
+    const FaceArgs F = cload(&args[t.p]);
+    face_avg_tile<D, N, PDE, A, TT, GT>(F, t.bx, t.yz & 0xffff, t.yz >> 16);
   }
 }
 

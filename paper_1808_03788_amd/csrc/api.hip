@@ -59,6 +59,7 @@ struct KClass {
   int D = 0;
   const void *face[3] = {nullptr, nullptr, nullptr};
   const void *update = nullptr, *cfl = nullptr, *detect = nullptr;
+  bool face_avg = false;                   // face integrals from time-averaged traces
   PredArgs *pargs = nullptr;               // device [np]
   DetArgs *dargs = nullptr;                // device [np], once detection is enabled
   FaceArgs *fargs[3] = {nullptr, nullptr, nullptr};
@@ -161,6 +162,7 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
     return fail(c, ADER_ERR_INVALID, w + "unknown precision");
   if (d.picard_iters < 0) return fail(c, ADER_ERR_INVALID, w + "picard_iters must be >= 0");
   if (d.guess < 0 || d.guess > 2) return fail(c, ADER_ERR_INVALID, w + "guess must be 0, 1 or 2");
+  if (d.face_avg != 0 && d.face_avg != 1) return fail(c, ADER_ERR_INVALID, w + "face_avg must be 0 or 1");
   if (!(d.cfl > 0.0) || d.cfl > 1.0) return fail(c, ADER_ERR_INVALID, w + "cfl must be in (0, 1]");
   return ADER_OK;
 }
@@ -288,6 +290,7 @@ PredArgs pred_args(const ProbState &s, int p) {
   a.acc_glob = s.acc;
   a.sweeps = s.sweeps;
   a.guess = s.desc.guess;
+  a.face_avg = s.desc.face_avg != 0;
   return a;
 }
 
@@ -397,7 +400,7 @@ ader_status build_class(ader_ctx *c, KClass &k) {
   std::vector<CflArgs> ca(np);
   std::vector<int64_t> ps(np + 1, 0), cs(np + 1, 0);
   std::vector<RowTile> ft, ut;
-  const int fpb = face_per_block(k.D, c->P[k.probs[0]].N);
+  const int fpb = k.face_avg ? face_avg_per_block(k.D, c->P[k.probs[0]].N) : face_per_block(k.D, c->P[k.probs[0]].N);
   for (int a = 0; a < 3; a++) fa[a].resize(np);
   for (int i = 0; i < np; i++) {
     const int p = k.probs[i];
@@ -777,7 +780,9 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     const size_t ub = (size_t)s.u_cnt * sizeof(double);
     const size_t gb = (size_t)s.E * s.m * s.nf * s.trace_elt;  // face integrals share the trace type
     if ((st = dalloc(c, (void **)&s.ustar, ub))) return bail(st);
-    const size_t tb = (size_t)s.u_cnt * s.trace_elt;
+    // traces per element and side: every time node, or the time averages
+    const int ncomp = d.pde == ADER_ELASTIC ? s.m : 2 * s.m;
+    const size_t tb = d.face_avg ? (size_t)s.E * ncomp * s.nf * s.trace_elt : (size_t)s.u_cnt * s.trace_elt;
     for (int a = 0; a < s.D; a++) {
       for (int sd = 0; sd < 2; sd++)
         if ((st = dalloc(c, (void **)&s.trace[a][sd], tb))) return bail(st);
@@ -829,14 +834,19 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     int k = 0;
     for (; k < (int)c->K.size(); k++) {
       const ProbState &r = c->P[c->K[k].probs[0]];
-      if (r.D == s.D && r.N == s.N && r.desc.pde == s.desc.pde && r.desc.prec == s.desc.prec) break;
+      if (r.D == s.D && r.N == s.N && r.desc.pde == s.desc.pde && r.desc.prec == s.desc.prec &&
+          (r.desc.face_avg != 0) == (s.desc.face_avg != 0))
+        break;
     }
     if (k == (int)c->K.size()) {
       KClass kc;
       kc.D = s.D;
       kc.pv = s.cand[0];
       const bool f64 = s.desc.prec == ADER_FP64;
-      for (int ax = 0; ax < 3; ax++) kc.face[ax] = f64 ? s.ks.face64[ax] : s.ks.face32[ax];
+      kc.face_avg = s.desc.face_avg != 0;
+      for (int ax = 0; ax < 3; ax++)
+        kc.face[ax] = kc.face_avg ? (f64 ? s.ks.faceavg64[ax] : s.ks.faceavg32[ax])
+                                  : (f64 ? s.ks.face64[ax] : s.ks.face32[ax]);
       kc.update = f64 ? s.ks.update64 : s.ks.update32;
       kc.cfl = s.ks.cfl;
       kc.detect = s.ks.detect;

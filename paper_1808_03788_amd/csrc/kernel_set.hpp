@@ -22,6 +22,8 @@ struct KernelSet {
   int npred = 0;
   const void *face64[3] = {nullptr, nullptr, nullptr};  // FP64 traces and face integrals
   const void *face32[3] = {nullptr, nullptr, nullptr};  // FP32 traces and face integrals
+  const void *faceavg64[3] = {nullptr, nullptr, nullptr};  // from time-averaged traces
+  const void *faceavg32[3] = {nullptr, nullptr, nullptr};
   const void *update64 = nullptr;                       // FP64 face integrals
   const void *update32 = nullptr;                       // FP32 face integrals
   const void *cfl = nullptr;
@@ -58,13 +60,19 @@ KernelSet make_kernel_set() {
   add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
   k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double, double>;
   k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float, float>;
+  k.faceavg64[0] = (const void *)&k_face_avg<D, N, PDE, 0, double, double>;
+  k.faceavg32[0] = (const void *)&k_face_avg<D, N, PDE, 0, float, float>;
   if constexpr (D > 1) {
     k.face64[1] = (const void *)&k_face<D, N, PDE, 1, double, double>;
     k.face32[1] = (const void *)&k_face<D, N, PDE, 1, float, float>;
+    k.faceavg64[1] = (const void *)&k_face_avg<D, N, PDE, 1, double, double>;
+    k.faceavg32[1] = (const void *)&k_face_avg<D, N, PDE, 1, float, float>;
   }
   if constexpr (D > 2) {
     k.face64[2] = (const void *)&k_face<D, N, PDE, 2, double, double>;
     k.face32[2] = (const void *)&k_face<D, N, PDE, 2, float, float>;
+    k.faceavg64[2] = (const void *)&k_face_avg<D, N, PDE, 2, double, double>;
+    k.faceavg32[2] = (const void *)&k_face_avg<D, N, PDE, 2, float, float>;
   }
   k.update64 = (const void *)&k_update<D, N, PDE, double>;
   k.update32 = (const void *)&k_update<D, N, PDE, float>;

@@ -381,3 +381,47 @@ def test_initial_guesses(A, orc, name, mk, init, steps, prec, guess):
     ug, _ = gpu_run(A, prob, u0, steps)
     uo, _ = orc_run(orc, mk("fp64", guess), u0, steps)
     check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec} guess={guess}")
+
+
+AVG_CASES = [
+    ("euler3d_N4", lambda pr: I.Problem(dim=3, N=4, nel=(3, 4, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr, face_avg=1),
+     lambda p: I.density_wave(p), 4),
+    ("euler3d_N3_ragged", lambda pr: I.Problem(dim=3, N=3, nel=(9, 3, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr,
+                                               face_avg=1), lambda p: I.fourier_modes(p), 4),
+    ("vortex2d_N3", lambda pr: I.vortex_problem(nel=8, N=3, prec=pr, face_avg=1), I.isentropic_vortex, 4),
+    ("elastic_N3", lambda pr: I.elastic_problem(nel=3, N=3, prec=pr, face_avg=1),
+     lambda p: I.stress_pulse(p, width=0.25), 4),
+    ("elastic_N5", lambda pr: I.elastic_problem(nel=2, N=5, prec=pr, face_avg=1),
+     lambda p: I.stress_pulse(p, width=0.3), 3),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,mk,init,steps", AVG_CASES, ids=[c[0] for c in AVG_CASES])
+def test_face_integrals_from_averaged_traces(A, orc, name, mk, init, steps, prec):
+    prob = mk(prec)
+    u0 = init(prob)
+    say(f"[face_avg] {name} {prec}")
+    ug, _ = gpu_run(A, prob, u0, steps)
+    uo, _ = orc_run(orc, mk("fp64"), u0, steps)
+    check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec} face_avg")
+
+
+def test_face_avg_and_literal_in_one_context(A, orc):
+    """The same mesh with and without averaged traces in one context: two
+    kernel classes, each matching the oracle."""
+    import torch
+    mk = lambda fa: I.Problem(dim=3, N=3, nel=(3, 3, 3), lo=(0, 0, 0), hi=(1, 1, 1), face_avg=fa)
+    probs = [mk(0), mk(1)]
+    inits = [I.density_wave(p) for p in probs]
+    ctx = A.Context(probs)
+    u = ctx.upload(inits)
+    for _ in range(3):
+        ctx.step(u, [1e9, 1e9])
+    torch.cuda.synchronize()
+    outs = ctx.download(u)
+    ctx.close()
+    for p, u0, ug in zip(probs, inits, outs):
+        uo, _ = orc_run(orc, p, u0, 3)
+        check(p, ug, uo, what=f"face_avg={p.face_avg}")
+    assert not np.array_equal(outs[0], outs[1])
