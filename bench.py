@@ -85,14 +85,19 @@ def sweeps_of(p) -> int:
     return p.picard or max(1, p.N + 1 - (p.guess or 0))
 
 
-def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8) -> dict:
+def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8, face_avg: bool = False) -> dict:
     """Algorithmic HBM bytes per element per step, per stage (elasticity,
-    m = 9, stores a face integral for each side of a face)."""
+    m = 9, stores a face integral for each side of a face; with averaged
+    traces a face node holds qbar and, for Euler, Fbar instead of every
+    time node)."""
     n = N + 1
     nd = n ** d
     nf = nd // n
     u = 8 * m * nd
-    trace = trace_bytes * m * nd            # one face trace block of one element
+    if face_avg:
+        trace = trace_bytes * (m if m == 9 else 2 * m) * nf
+    else:
+        trace = trace_bytes * m * nd        # one face trace block of one element
     g = trace_bytes * m * nf                 # one face integral block (stored like the traces)
     return {
         "cfl": u,
@@ -126,7 +131,7 @@ def traffic_from_profiles(prec: str):
     return rec.get(prec, {}).get("bytes_per_launch")
 
 
-def cpu_baseline(workload: str = "density", seconds: float = 12.0, guess: int = 0) -> dict:
+def cpu_baseline(workload: str = "density", seconds: float = 12.0, guess: int = 0, face_avg: int = 0) -> dict:
     """The FP64 oracle on a bounded sample of the workload (same degree,
     PDE and initial-data recipe on a smaller mesh, or a few of the batched
     problems), as many steps as fit in about `seconds` (at least one)."""
@@ -137,11 +142,13 @@ def cpu_baseline(workload: str = "density", seconds: float = 12.0, guess: int = 
         probs = [p for p, _ in items]
         for p in probs:
             p.guess = guess
+            p.face_avg = face_avg
         us = [I.density_wave(p, **kw) for p, kw in items]
         what = "the 8 smallest of the 256 batched problems"
     else:
         probs, us, _ = make_workload(workload, "fp64", I, nel={"density": 16, "elastic": 12,
-                                                               "fourier": 32}[workload], guess=guess)
+                                                               "fourier": 32}[workload], guess=guess,
+                                     face_avg=face_avg)
         what = f"{probs[0].nel[0]}^3 elements of the same recipe"
     ts = [0.0] * len(probs)
     steps = 0
@@ -169,23 +176,23 @@ def note(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0):
+def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0, face_avg=0):
     """(problems, initial states, description) of a workload."""
     if workload == "density":
         prob = I.density_wave_problem(nel=nel or 64, N=4 if degree is None else degree, prec=prec,
-                                      picard=picard, guess=guess)
+                                      picard=picard, guess=guess, face_avg=face_avg)
         desc = (f"3-D Euler density wave, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
                 f"CFL 0.9, 1e-3 seeded noise")
         return [prob], [I.density_wave(prob)], desc
     if workload == "elastic":
         prob = I.elastic_problem(nel=nel or 48, N=5 if degree is None else degree, prec=prec, picard=picard,
-                                 guess=guess)
+                                 guess=guess, face_avg=face_avg)
         desc = (f"3-D linear elasticity, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, "
                 f"4 seeded layers (rho 2000-3000, cp 3000-6000, cs = cp/sqrt 3), stress pulse width 0.05")
         return [prob], [I.stress_pulse(prob)], desc
     if workload == "fourier":
         prob = I.fourier_problem(nel=nel or 128, N=3 if degree is None else degree, prec=prec, picard=picard,
-                                 guess=guess)
+                                 guess=guess, face_avg=face_avg)
         desc = (f"3-D Euler, periodic unit cube, {prob.nel[0]}^3 elements, N={prob.N}, 8 seeded Fourier "
                 f"modes of amplitude 0.05 on rho = 1, p = 1")
         return [prob], [I.fourier_modes(prob)], desc
@@ -195,6 +202,7 @@ def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0):
         for p in probs:
             p.picard = picard
             p.guess = guess
+            p.face_avg = face_avg
         inits = [I.density_wave(p, **kw) for p, kw in items]
         desc = ("256 seeded 3-D Euler density waves, meshes 8^3..32^3, N in 2..6, one context, "
                 "batched launches per degree, captured-graph replays")
@@ -203,11 +211,11 @@ def make_workload(workload, prec, I, nel=None, degree=None, picard=0, guess=0):
 
 
 def run_path(workload, prec, steps, warmup, I, ader, torch, nel=None, degree=None, picard=0,
-             graph_steps=0, guess=0, detect=False):
+             graph_steps=0, guess=0, detect=False, face_avg=0):
     """Time `steps` steps (or graph replays of `graph_steps` steps each) of
     one precision mode; returns the timings, stage times and the final state
     (device tensor)."""
-    probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard, guess)
+    probs, inits, desc = make_workload(workload, prec, I, nel, degree, picard, guess, face_avg)
     note(f"{prec}: {len(probs)} problem(s) generated")
     ctx = ader.Context(probs)
     if detect:
@@ -284,7 +292,7 @@ def stage_summary(res, trace_bytes):
         if not cnt:
             continue
         avg = ms / cnt
-        byts = sum(step_bytes(p.dim, p.N, p.m, trace_bytes)[k] * p.E for p in res["probs"])
+        byts = sum(step_bytes(p.dim, p.N, p.m, trace_bytes, bool(p.face_avg))[k] * p.E for p in res["probs"])
         gbs = byts / (avg * 1e-3) / 1e9 if avg > 0 else None
         out[k] = {"avg_ms": round(avg, 4), "alg_GB_per_s": round(gbs, 1) if gbs else None}
     return out
@@ -307,6 +315,8 @@ def main():
                     help="steps per captured-graph replay (0: plain ader_step; -1: 10 for batched, else 0)")
     ap.add_argument("--detect", action="store_true",
                     help="a posteriori detection of troubled elements after every step (timed with the update)")
+    ap.add_argument("--face-avg", action="store_true",
+                    help="face integrals from time-averaged traces")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device copy (calibrates HBM byte counters)")
@@ -323,7 +333,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     gs = args.graph_steps if args.graph_steps >= 0 else (10 if args.workload == "batched" else 0)
     kw = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree, picard=args.picard,
-              graph_steps=gs, guess=args.guess, detect=args.detect)
+              graph_steps=gs, guess=args.guess, detect=args.detect, face_avg=int(args.face_avg))
     ref = run_path(args.workload, "fp64", args.steps, args.warmup, I, ader, torch, **kw)
     head = ref if args.prec == "fp64" else run_path(args.workload, args.prec, args.steps, args.warmup, I,
                                                     ader, torch, **kw)
@@ -366,6 +376,7 @@ def main():
     else:
         config.update(degrees=sorted({p.N for p in probs}), steps_per_replay=gs)
     config["detection"] = bool(args.detect)
+    config["face_avg"] = bool(args.face_avg)
     line = {
         "metric": METRIC,
         "value": head["value"],
@@ -410,7 +421,7 @@ def main():
         torch.cuda.synchronize()
         line["calib_copy_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.workload, guess=args.guess)
+        line["cpu_baseline"] = cpu_baseline(args.workload, guess=args.guess, face_avg=int(args.face_avg))
     print(json.dumps(line), flush=True)
 
 

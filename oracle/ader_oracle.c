@@ -584,29 +584,27 @@ static void element_corrector(const orc_problem *p, const setup_t *s, int e, con
       for (int i = 0; i < m * nd; i++) G[i] = 0.0;
       for (int k = 0; k < nd && p->face_avg; k++) {
         if (axis_index(s, k, a) != 0) continue;
-        /* time averages of the traces and of their fluxes on this face node */
+        /* time averages of the traces, and the face values of the
+         * time-averaged nodal fluxes, on this face node */
         double qi[MAXM], qo[MAXM], Fi[MAXM], Fo[MAXM];
         for (int v = 0; v < m; v++) qi[v] = qo[v] = Fi[v] = Fo[v] = 0.0;
-        for (int l0 = 0; l0 < n; l0++) {
-          double qin[MAXM], qout[MAXM], f1[MAXM], f2[MAXM];
-          for (int v = 0; v < m; v++) {
-            double si = 0.0, so = 0.0;
-            for (int j = 0; j < n; j++) {
-              si += phin[j] * q[(v * n + l0) * nd + k + j * s->str[a]];
-              so += phout[j] * qn[(v * n + l0) * nd + k + j * s->str[a]];
+        for (int l0 = 0; l0 < n; l0++)
+          for (int j = 0; j < n; j++) {
+            const int kj = k + j * s->str[a];
+            double vin[MAXM], vout[MAXM], f1[MAXM], f2[MAXM];
+            for (int v = 0; v < m; v++) {
+              vin[v] = q[(v * n + l0) * nd + kj];
+              vout[v] = qn[(v * n + l0) * nd + kj];
             }
-            qin[v] = si;
-            qout[v] = so;
+            pde_flux(p, s, vin, a, f1);
+            pde_flux(p, s, vout, a, f2);
+            for (int v = 0; v < m; v++) {
+              qi[v] += s->w[l0] * phin[j] * vin[v];
+              qo[v] += s->w[l0] * phout[j] * vout[v];
+              Fi[v] += s->w[l0] * phin[j] * f1[v];
+              Fo[v] += s->w[l0] * phout[j] * f2[v];
+            }
           }
-          pde_flux(p, s, qin, a, f1);
-          pde_flux(p, s, qout, a, f2);
-          for (int v = 0; v < m; v++) {
-            qi[v] += s->w[l0] * qin[v];
-            qo[v] += s->w[l0] * qout[v];
-            Fi[v] += s->w[l0] * f1[v];
-            Fo[v] += s->w[l0] * f2[v];
-          }
-        }
         double D[MAXM];
         dminus_avg(p, s, qi, qo, Fi, Fo, mat, matn, a, sgn, D);
         for (int v = 0; v < m; v++) G[v * nd + k] = D[v];

@@ -833,61 +833,67 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
   }
 }
 
-// Time-averaged trace of one face node on the face of axis A at side s
-// (x_A = 0 or 1): qbar = sum_l0 w_l0 q_s(l0) and, for Euler, the averaged
-// normal flux Fbar_A = sum_l0 w_l0 F_A(q_s(l0)), with q_s(l0) the
-// boundary-extrapolated state; stored as TT in [avg_comps][NF].
+// Time-averaged traces of one face node (kf) of the faces normal to axis
+// A, both sides: qbar = sum_j phi_j(side) Qbar(node j), where Qbar is the
+// time average sum_l0 w_l0 q(l0) at the volume nodes (read from qf, or
+// given as QB), and for Euler Fbar = sum_j phi_j(side) FB_A(node j), the
+// boundary value of the time-averaged nodal flux of the volume term.
+// Stored as TT in [avg_comps][NF] per element and side.
 template <int D, int N, class PDE, int A, typename TT>
-__device__ __forceinline__ void trace_avg_node(PArg &P, const double *sq, int64_t e, int side, int kf) {
+__device__ __forceinline__ void trace_avg_node(PArg &P, const double *qf, const double *QB, const double *FB,
+                                               int64_t e, int kf) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A), NC = avg_comps<PDE>();
   const int base = kf % ST + (kf / ST) * ST * n;
-  const double *phi = side ? P.ops->F1 : P.ops->F0;
-  double qb[M], fb[M];
+  TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(NC * NF) + kf;
+  TT *t1 = (TT *)P.trace[A][1] + e * (int64_t)(NC * NF) + kf;
 #pragma unroll
-  for (int v = 0; v < M; v++) qb[v] = fb[v] = 0.0;
-  for (int l0 = 0; l0 < n; l0++) {
-    double qv[M];
+  for (int v = 0; v < M; v++) {
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int v = 0; v < M; v++) {
-      double a = 0.0;
+    for (int j = 0; j < n; j++) {
+      double qb;
+      if (QB) {
+        qb = QB[v * ND + base + j * ST];
+      } else {
+        qb = 0.0;
 #pragma unroll
-      for (int j = 0; j < n; j++) a += cload(&phi[j]) * sq[v * NST + l0 * ND + base + j * ST];
-      qv[v] = a;
+        for (int l0 = 0; l0 < n; l0++) qb += cload(&P.ops->w[l0]) * qf[v * NST + l0 * ND + base + j * ST];
+      }
+      a0 += cload(&P.ops->F0[j]) * qb;
+      a1 += cload(&P.ops->F1[j]) * qb;
     }
-    const double wl = cload(&P.ops->w[l0]);
-#pragma unroll
-    for (int v = 0; v < M; v++) qb[v] += wl * qv[v];
+    t0[v * NF] = (TT)a0;
+    t1[v * NF] = (TT)a1;
     if constexpr (!PDE::kElastic) {
-      double F[M];
-      euler_flux<D, A, double>(qv, P.g.gamma - 1.0, F);
+      double f0 = 0.0, f1 = 0.0;
 #pragma unroll
-      for (int v = 0; v < M; v++) fb[v] += wl * F[v];
+      for (int j = 0; j < n; j++) {
+        const double fb = FB[(A * M + v) * ND + base + j * ST];
+        f0 += cload(&P.ops->F0[j]) * fb;
+        f1 += cload(&P.ops->F1[j]) * fb;
+      }
+      t0[(M + v) * NF] = (TT)f0;
+      t1[(M + v) * NF] = (TT)f1;
     }
   }
-  TT *t = (TT *)P.trace[A][side] + e * (int64_t)(NC * NF);
-#pragma unroll
-  for (int v = 0; v < M; v++) t[v * NF + kf] = (TT)qb[v];
-  if constexpr (!PDE::kElastic)
-#pragma unroll
-    for (int v = 0; v < M; v++) t[(M + v) * NF + kf] = (TT)fb[v];
 }
 
 // Averaged traces of all 2D faces: wavefront W takes axis W (and W + BS/64),
-// one lane per (side, face node).
+// one lane per face node (both sides).
 template <int D, int N, class PDE, typename TT, int BS>
-__device__ __forceinline__ void traces_avg(PArg &P, const double *sq, int64_t e) {
+__device__ __forceinline__ void traces_avg(PArg &P, const double *qf, const double *QB, const double *FB,
+                                           int64_t e) {
   constexpr int NF = Shape<D, N>::NF;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (int A = wave; A < D; A += BS / 64)
-    for (int it = lane; it < 2 * NF; it += 64) {
-      const int side = it / NF, kf = it - side * NF;
-      if (A == 0) trace_avg_node<D, N, PDE, 0, TT>(P, sq, e, side, kf);
+    for (int kf = lane; kf < NF; kf += 64) {
+      if (A == 0) trace_avg_node<D, N, PDE, 0, TT>(P, qf, QB, FB, e, kf);
       else if (A == 1) {
-        if constexpr (D > 1) trace_avg_node<D, N, PDE, 1, TT>(P, sq, e, side, kf);
+        if constexpr (D > 1) trace_avg_node<D, N, PDE, 1, TT>(P, qf, QB, FB, e, kf);
       } else {
-        if constexpr (D > 2) trace_avg_node<D, N, PDE, 2, TT>(P, sq, e, side, kf);
+        if constexpr (D > 2) trace_avg_node<D, N, PDE, 2, TT>(P, qf, QB, FB, e, kf);
       }
     }
 }
@@ -903,30 +909,36 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   if (qo)
     for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
-  if (P.face_avg) {
-    traces_avg<D, N, PDE, TT, BS>(P, qf, e);
-  } else {
+  if (!P.face_avg) {
     traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
     if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
     if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
   }
   double *us = P.ustar + e * (int64_t)(M * ND);
-  if constexpr (N == 0) {
-    for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
-  } else if constexpr (!PDE::kElastic) {
-    euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
-    __syncthreads();
-    euler_volume_axis<D, N, PDE, 0, BS>(P, scratch);
-    __syncthreads();
-    if constexpr (D > 1) {
-      euler_volume_axis<D, N, PDE, 1, BS>(P, scratch);
+  if constexpr (!PDE::kElastic) {
+    if (N > 0 || P.face_avg) {
+      euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
       __syncthreads();
     }
-    if constexpr (D > 2) {
-      euler_volume_axis<D, N, PDE, 2, BS>(P, scratch);
+    if (P.face_avg) {  // before the volume passes overwrite FB[0]
+      traces_avg<D, N, PDE, TT, BS>(P, qf, nullptr, scratch, e);
       __syncthreads();
     }
-    ustar_update<D, N, PDE, BS>(scratch, ureg, us, dt);
+    if constexpr (N == 0) {
+      for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
+    } else {
+      euler_volume_axis<D, N, PDE, 0, BS>(P, scratch);
+      __syncthreads();
+      if constexpr (D > 1) {
+        euler_volume_axis<D, N, PDE, 1, BS>(P, scratch);
+        __syncthreads();
+      }
+      if constexpr (D > 2) {
+        euler_volume_axis<D, N, PDE, 2, BS>(P, scratch);
+        __syncthreads();
+      }
+      ustar_update<D, N, PDE, BS>(scratch, ureg, us, dt);
+    }
   } else {
     for (int i = threadIdx.x; i < M * ND; i += BS) {
       const int v = i / ND, k = i - v * ND;
@@ -936,7 +948,12 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
       scratch[i] = a;
     }
     __syncthreads();
-    elastic_volume_update<D, N, BS>(P, scratch, ue, us, dt, irho, lam, mu);
+    if (P.face_avg) traces_avg<D, N, PDE, TT, BS>(P, qf, scratch, nullptr, e);
+    if constexpr (N == 0) {
+      for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
+    } else {
+      elastic_volume_update<D, N, BS>(P, scratch, ue, us, dt, irho, lam, mu);
+    }
   }
 }
 
