@@ -833,69 +833,66 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
   }
 }
 
-// Time-averaged traces of one face node (kf) of the faces normal to axis
-// A, both sides: qbar = sum_j phi_j(side) Qbar(node j), where Qbar is the
-// time average sum_l0 w_l0 q(l0) at the volume nodes (read from qf, or
+// Time-averaged traces of variable v at face node kf of the faces normal to
+// axis A, both sides: qbar = sum_j phi_j(side) Qbar(node j), where Qbar is
+// the time average sum_l0 w_l0 q(l0) at the volume nodes (read from qf, or
 // given as QB), and for Euler Fbar = sum_j phi_j(side) FB_A(node j), the
 // boundary value of the time-averaged nodal flux of the volume term.
 // Stored as TT in [avg_comps][NF] per element and side.
 template <int D, int N, class PDE, int A, typename TT>
-__device__ __forceinline__ void trace_avg_node(PArg &P, const double *qf, const double *QB, const double *FB,
-                                               int64_t e, int kf) {
+__device__ __forceinline__ void trace_avg_value(PArg &P, const double *qf, const double *QB, const double *FB,
+                                                int64_t e, int v, int kf) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A), NC = avg_comps<PDE>();
   const int base = kf % ST + (kf / ST) * ST * n;
   TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(NC * NF) + kf;
   TT *t1 = (TT *)P.trace[A][1] + e * (int64_t)(NC * NF) + kf;
+  double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-  for (int v = 0; v < M; v++) {
-    double a0 = 0.0, a1 = 0.0;
+  for (int j = 0; j < n; j++) {
+    double qb;
+    if (QB) {
+      qb = QB[v * ND + base + j * ST];
+    } else {
+      qb = 0.0;
+#pragma unroll
+      for (int l0 = 0; l0 < n; l0++) qb += cload(&P.ops->w[l0]) * qf[v * NST + l0 * ND + base + j * ST];
+    }
+    a0 += cload(&P.ops->F0[j]) * qb;
+    a1 += cload(&P.ops->F1[j]) * qb;
+  }
+  t0[v * NF] = (TT)a0;
+  t1[v * NF] = (TT)a1;
+  if constexpr (!PDE::kElastic) {
+    double f0 = 0.0, f1 = 0.0;
 #pragma unroll
     for (int j = 0; j < n; j++) {
-      double qb;
-      if (QB) {
-        qb = QB[v * ND + base + j * ST];
-      } else {
-        qb = 0.0;
-#pragma unroll
-        for (int l0 = 0; l0 < n; l0++) qb += cload(&P.ops->w[l0]) * qf[v * NST + l0 * ND + base + j * ST];
-      }
-      a0 += cload(&P.ops->F0[j]) * qb;
-      a1 += cload(&P.ops->F1[j]) * qb;
+      const double fb = FB[(A * M + v) * ND + base + j * ST];
+      f0 += cload(&P.ops->F0[j]) * fb;
+      f1 += cload(&P.ops->F1[j]) * fb;
     }
-    t0[v * NF] = (TT)a0;
-    t1[v * NF] = (TT)a1;
-    if constexpr (!PDE::kElastic) {
-      double f0 = 0.0, f1 = 0.0;
-#pragma unroll
-      for (int j = 0; j < n; j++) {
-        const double fb = FB[(A * M + v) * ND + base + j * ST];
-        f0 += cload(&P.ops->F0[j]) * fb;
-        f1 += cload(&P.ops->F1[j]) * fb;
-      }
-      t0[(M + v) * NF] = (TT)f0;
-      t1[(M + v) * NF] = (TT)f1;
-    }
+    t0[(M + v) * NF] = (TT)f0;
+    t1[(M + v) * NF] = (TT)f1;
   }
 }
 
-// Averaged traces of all 2D faces: wavefront W takes axis W (and W + BS/64),
-// one lane per face node (both sides).
+// Averaged traces of all 2D faces: one thread per (axis, variable, face
+// node), both sides.
 template <int D, int N, class PDE, typename TT, int BS>
 __device__ __forceinline__ void traces_avg(PArg &P, const double *qf, const double *QB, const double *FB,
                                            int64_t e) {
-  constexpr int NF = Shape<D, N>::NF;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int A = wave; A < D; A += BS / 64)
-    for (int kf = lane; kf < NF; kf += 64) {
-      if (A == 0) trace_avg_node<D, N, PDE, 0, TT>(P, qf, QB, FB, e, kf);
-      else if (A == 1) {
-        if constexpr (D > 1) trace_avg_node<D, N, PDE, 1, TT>(P, qf, QB, FB, e, kf);
-      } else {
-        if constexpr (D > 2) trace_avg_node<D, N, PDE, 2, TT>(P, qf, QB, FB, e, kf);
-      }
+  constexpr int M = PDE::M, NF = Shape<D, N>::NF;
+  for (int it = threadIdx.x; it < D * M * NF; it += BS) {
+    const int A = it / (M * NF), r = it - A * (M * NF);
+    const int v = r / NF, kf = r - v * NF;
+    if (A == 0) trace_avg_value<D, N, PDE, 0, TT>(P, qf, QB, FB, e, v, kf);
+    else if (A == 1) {
+      if constexpr (D > 1) trace_avg_value<D, N, PDE, 1, TT>(P, qf, QB, FB, e, v, kf);
+    } else {
+      if constexpr (D > 2) trace_avg_value<D, N, PDE, 2, TT>(P, qf, QB, FB, e, v, kf);
     }
+  }
 }
 
 // Predictor outputs from the final FP64 iterate qf: optional qhat copy, the
