@@ -26,6 +26,14 @@ __device__ __forceinline__ T cload(const T *p) {
   }
 }
 
+// Buffer pointers read from argument records are generic; accesses through
+// these global-address-space views compile to global (not flat) loads and
+// stores, with scalar base addresses.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p) {
+  return (__attribute__((address_space(1))) T *)p;
+}
+
 // Tiles of a batched launch.  Problem p of the batch owns the tiles
 // [start[p], start[p+1]); a kernel walks the tiles start[0]..start[np]-1
 // with a grid-stride loop (persistent workgroups), so one launch covers any
@@ -1134,8 +1142,8 @@ __device__ __forceinline__ void face_tile(const FaceArgs &F, int bx, int iy, int
     const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
     const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
     const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
-    const TT *tm = (const TT *)F.trace1 + e * (int64_t)(M * ND) + r;
-    const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(M * ND) + r;
+    const auto *tm = as_global((const TT *)F.trace1 + e * (int64_t)(M * ND) + r);
+    const auto *tp = as_global((const TT *)F.trace0 + eR * (int64_t)(M * ND) + r);
     double qm[M], qp[M];
 #pragma unroll
     for (int v = 0; v < M; v++) {
@@ -1154,8 +1162,9 @@ __device__ __forceinline__ void face_tile(const FaceArgs &F, int bx, int iy, int
         sD[0][f][v][r] = wl * (0.5 * (Fp[v] + Fm[v]) - 0.5 * smax * (qp[v] - qm[v]));
     } else {
       // material path integral with the 3-point Gauss-Legendre rule on [0,1]
-      const double rL = F.mat[3 * e], lL = F.mat[3 * e + 1], mL = F.mat[3 * e + 2];
-      const double rR = F.mat[3 * eR], lR = F.mat[3 * eR + 1], mR = F.mat[3 * eR + 2];
+      const auto *mat = as_global(F.mat);
+      const double rL = mat[3 * e], lL = mat[3 * e + 1], mL = mat[3 * e + 2];
+      const double rR = mat[3 * eR], lR = mat[3 * eR + 1], mR = mat[3 * eR + 2];
       const double gs[3] = {0.5 - 0.1 * sqrt(15.0), 0.5, 0.5 + 0.1 * sqrt(15.0)};
       const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
       double irho = 0.0, lam = 0.0, mu = 0.0;
@@ -1190,7 +1199,7 @@ __device__ __forceinline__ void face_tile(const FaceArgs &F, int bx, int iy, int
       double acc = 0.0;
 #pragma unroll
       for (int l0 = 0; l0 < n; l0++) acc += sD[g][f][v][l0 * NF + kf];
-      ((GT *)(g == 0 ? F.GL : F.GR))[e * (int64_t)(M * NF) + r] = (GT)acc;
+      as_global((GT *)(g == 0 ? F.GL : F.GR))[e * (int64_t)(M * NF) + r] = (GT)acc;
     }
   }
 }
@@ -1237,15 +1246,15 @@ __device__ __forceinline__ void face_avg_tile(const FaceArgs &F, int bx, int iy,
     const int jy = (A == 1) ? (iy + 1 == ny ? 0 : iy + 1) : iy;
     const int jz = (A == 2) ? (iz + 1 == nz ? 0 : iz + 1) : iz;
     const int64_t eR = jx + (int64_t)nx * (jy + (int64_t)ny * jz);
-    const TT *tm = (const TT *)F.trace1 + e * (int64_t)(NC * NF) + kf;
-    const TT *tp = (const TT *)F.trace0 + eR * (int64_t)(NC * NF) + kf;
+    const auto *tm = as_global((const TT *)F.trace1 + e * (int64_t)(NC * NF) + kf);
+    const auto *tp = as_global((const TT *)F.trace0 + eR * (int64_t)(NC * NF) + kf);
     double qm[M], qp[M];
 #pragma unroll
     for (int v = 0; v < M; v++) {
       qm[v] = (double)tm[v * NF];
       qp[v] = (double)tp[v * NF];
     }
-    GT *gl = (GT *)F.GL + e * (int64_t)(M * NF) + kf;
+    auto *gl = as_global((GT *)F.GL + e * (int64_t)(M * NF) + kf);
     if constexpr (!PDE::kElastic) {
       const double gamma = F.g.gamma;
       const double smax = fmax(euler_speed<D, A>(qm, gamma), euler_speed<D, A>(qp, gamma));
@@ -1253,8 +1262,9 @@ __device__ __forceinline__ void face_avg_tile(const FaceArgs &F, int bx, int iy,
       for (int v = 0; v < M; v++)
         gl[v * NF] = (GT)(0.5 * ((double)tp[(M + v) * NF] + (double)tm[(M + v) * NF]) - 0.5 * smax * (qp[v] - qm[v]));
     } else {
-      const double rL = F.mat[3 * e], lL = F.mat[3 * e + 1], mL = F.mat[3 * e + 2];
-      const double rR = F.mat[3 * eR], lR = F.mat[3 * eR + 1], mR = F.mat[3 * eR + 2];
+      const auto *mat = as_global(F.mat);
+      const double rL = mat[3 * e], lL = mat[3 * e + 1], mL = mat[3 * e + 2];
+      const double rR = mat[3 * eR], lR = mat[3 * eR + 1], mR = mat[3 * eR + 2];
       const double gs[3] = {0.5 - 0.1 * sqrt(15.0), 0.5, 0.5 + 0.1 * sqrt(15.0)};
       const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
       double irho = 0.0, lam = 0.0, mu = 0.0;
@@ -1269,7 +1279,7 @@ __device__ __forceinline__ void face_avg_tile(const FaceArgs &F, int bx, int iy,
 #pragma unroll
       for (int v = 0; v < M; v++) dq[v] = qp[v] - qm[v];
       elastic_bg<A, double>(dq, irho, lam, mu, bd);
-      GT *gr = (GT *)F.GR + e * (int64_t)(M * NF) + kf;
+      auto *gr = as_global((GT *)F.GR + e * (int64_t)(M * NF) + kf);
 #pragma unroll
       for (int v = 0; v < M; v++) {
         gl[v * NF] = (GT)(0.5 * (bd[v] - smax * dq[v]));
@@ -1335,13 +1345,15 @@ __device__ __forceinline__ void update_nodes(const UpdArgs &U, int t, int iy, in
     cm[A] = PDE::kConservative ? -U.g.inv_h[A] * cload(&U.ops->L0[ka]) : U.g.inv_h[A] * cload(&U.ops->L0[ka]);
   }
   const int64_t base = e * (M * ND) + k;
-  double *u = ubuf + U.u_off;
+  auto *u = as_global(ubuf + U.u_off);
+  const auto *ustar = as_global(U.ustar);
 #pragma unroll
   for (int v = 0; v < M; v++) {
     double acc = 0.0;
 #pragma unroll
-    for (int A = 0; A < D; A++) acc += cp[A] * (double)gp[A][v * NF] + cm[A] * (double)gm[A][v * NF];
-    const double us = U.ustar[base + v * ND];
+    for (int A = 0; A < D; A++)
+      acc += cp[A] * (double)as_global(gp[A])[v * NF] + cm[A] * (double)as_global(gm[A])[v * NF];
+    const double us = ustar[base + v * ND];
     u[base + v * ND] = dt == 0.0 ? us : us - dt * acc;
   }
 }
@@ -1393,7 +1405,7 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
       vmin[v] = INFINITY;
       vmax[v] = -INFINITY;
     }
-    const double *ue = u + C.u_off + e * (int64_t)(M * ND);
+    const auto *ue = as_global(u + C.u_off + e * (int64_t)(M * ND));
     for (int k = lane; k < ND; k += 64) {
       double q[M];
 #pragma unroll
@@ -1440,8 +1452,8 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
           vmax[v] = fmax(vmax[v], __shfl_xor(vmax[v], off, 64));
         }
         if (lane == 0) {
-          C.summ[(e * M + v) * 2] = vmin[v];
-          C.summ[(e * M + v) * 2 + 1] = vmax[v];
+          as_global(C.summ)[(e * M + v) * 2] = vmin[v];
+          as_global(C.summ)[(e * M + v) * 2 + 1] = vmax[v];
         }
       }
     }
@@ -1500,7 +1512,7 @@ __device__ __forceinline__ void detect_row(const DetArgs &A, int64_t row, const 
   const int iy = (int)(row % ny), iz = (int)(row / ny);
   for (int ix = wave; ix < nx; ix += kBlock / 64) {
     const int64_t e = row * nx + ix;
-    const double *ue = u + A.u_off + e * (int64_t)(M * ND);
+    const auto *ue = as_global(u + A.u_off + e * (int64_t)(M * ND));
     int f = 0;
     for (int k = lane; k < ND; k += 64) {
       double q[M];
@@ -1522,8 +1534,8 @@ __device__ __forceinline__ void detect_row(const DetArgs &A, int64_t row, const 
     }
 #pragma unroll
     for (int v = 0; v < M; v++) {
-      double lo = lane < NB ? A.summ[(en * M + v) * 2] : INFINITY;
-      double hi = lane < NB ? A.summ[(en * M + v) * 2 + 1] : -INFINITY;
+      double lo = lane < NB ? as_global(A.summ)[(en * M + v) * 2] : INFINITY;
+      double hi = lane < NB ? as_global(A.summ)[(en * M + v) * 2 + 1] : -INFINITY;
       for (int off = 32; off > 0; off >>= 1) {
         lo = fmin(lo, __shfl_xor(lo, off, 64));
         hi = fmax(hi, __shfl_xor(hi, off, 64));
@@ -1536,7 +1548,7 @@ __device__ __forceinline__ void detect_row(const DetArgs &A, int64_t row, const 
       }
     }
     for (int off = 32; off > 0; off >>= 1) f |= __shfl_xor(f, off, 64);
-    if (lane == 0) A.flags[e] = f;
+    if (lane == 0) as_global(A.flags)[e] = f;
   }
 }
 
