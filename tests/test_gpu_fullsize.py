@@ -1,0 +1,140 @@
+"""The benchmark workloads at full size, sampled against the oracle.
+
+Each workload is built by bench.make_workload at its full size and advanced
+one step on the GPU the way the benchmark runs it (autotuned kernel classes;
+the 256-problem batch through a captured-graph replay).  A seeded sample of
+elements is then checked against the oracle run on each element's 3x3x3
+periodic neighbourhood with the GPU's time step: the update of an element
+depends only on its face neighbours, so the centre element of that sub-mesh
+is computed exactly as in the full mesh.  The error is the max-norm over the
+element's values divided by the max-norm of the whole initial field: FP64
+path <= 1e-12, FP32 sweeps <= 1e-6, BF16 contraction inputs <= 1e-2 (the
+bound the variant tests use for BF16).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1808_03788_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import bench  # noqa: E402  (workload recipes of the benchmark)
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1808_03788_amd import ader
+    ader.lib()
+    return ader
+
+
+def neighbourhood(prob, ix, iy, iz):
+    nx, ny, nz = prob.nel
+    return [((ix + dx) % nx) + nx * (((iy + dy) % ny) + ny * ((iz + dz) % nz))
+            for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)]
+
+
+def oracle_centre(orc, prob, u0, ids, dt):
+    """One oracle step of the 3x3x3 sub-mesh `ids` with time step dt; returns
+    the centre element's new state."""
+    h = prob.h
+    sub = I.Problem(dim=3, N=prob.N, nel=(3, 3, 3), lo=(0.0, 0.0, 0.0),
+                    hi=(3 * h[0], 3 * h[1], 3 * h[2]), pde=prob.pde, gamma=prob.gamma,
+                    picard=prob.picard, cfl=prob.cfl, prec="fp64", guess=prob.guess,
+                    face_avg=prob.face_avg)
+    if prob.pde == "elastic":
+        sub.material = prob.material[ids]
+    usub = u0[ids]
+    q = orc.predictor(sub, usub, dt)
+    return orc.corrector(sub, usub, q, dt)[13]
+
+
+def picks_for(prob, seed, count, hot=None):
+    nx, ny, nz = prob.nel
+    rng = np.random.default_rng(seed)
+    out = [(0, 0, 0), (nx - 1, ny - 1, nz - 1)]
+    if hot is not None:  # elements where the initial data are not small
+        out.append(tuple(int(min(c * n, n - 1)) for c, n in zip(hot, prob.nel)))
+    out += [(int(rng.integers(0, nx)), int(rng.integers(0, ny)), int(rng.integers(0, nz)))
+            for _ in range(count)]
+    return out
+
+
+def check_sampled(orc, prob, u0, ug, dt, picks, tol, what):
+    scale = np.abs(u0).max()
+    worst = 0.0
+    for (ix, iy, iz) in picks:
+        ids = neighbourhood(prob, ix, iy, iz)
+        ref = oracle_centre(orc, prob, u0, ids, dt)
+        err = np.abs(ug[ids[13]] - ref).max() / scale
+        worst = max(worst, err)
+        assert err <= tol, (what, (ix, iy, iz), err)
+    say(f"  {what}: {len(picks)} elements, worst {worst:.2e} (tol {tol:g})")
+
+
+CASES = [
+    ("density", "fp32", None),
+    ("elastic", "fp64", (0.5, 0.5, 0.375)),
+    ("elastic", "fp32", (0.5, 0.5, 0.375)),
+    ("elastic", "bf16", (0.5, 0.5, 0.375)),
+    ("fourier", "fp64", None),
+    ("fourier", "fp32", None),
+]
+
+
+@pytest.mark.parametrize("workload,prec,hot", CASES, ids=[f"{c[0]}-{c[1]}" for c in CASES])
+def test_full_size_sampled(A, orc, workload, prec, hot):
+    import torch
+    probs, inits, desc = bench.make_workload(workload, prec, I, None, None, 0, 0, 0)
+    prob, u0 = probs[0], inits[0]
+    say(f"[full size] {workload} {prec}: {desc}")
+    ctx = A.Context([prob])
+    try:
+        u = ctx.upload([u0])
+        ctx.step(u, [1e9])
+        torch.cuda.synchronize()
+        dt = float(ctx.last_dt()[0])
+        say(f"  {A.ader_describe(ctx.ctx, 0).split()[0]} dt={dt:.6e}")
+        assert abs(dt - orc.cfl_dt(prob, u0)) <= 1e-14 * dt
+        ug = ctx.download(u)[0]
+    finally:
+        ctx.close()
+    check_sampled(orc, prob, u0, ug, dt, picks_for(prob, 11, 6, hot), TOL[prec], f"{workload} {prec}")
+
+
+def test_batched_full_size_sampled_graph(A, orc):
+    """The 256-problem batch (degrees 2..6, meshes 8^3..32^3) in one context,
+    one step through a captured-graph replay; 8 seeded problems, 3 elements
+    each."""
+    import torch
+    probs, inits, desc = bench.make_workload("batched", "fp32", I, None, None, 0, 0, 0)
+    say(f"[full size] batched: {desc}")
+    ctx = A.Context(probs)
+    try:
+        u = ctx.upload(inits)
+        ctx.run(u, [1e9] * len(probs), 1)
+        torch.cuda.synchronize()
+        dts = np.array(ctx.last_dt(), dtype=np.float64)
+        outs = ctx.download(u)
+    finally:
+        ctx.close()
+    rng = np.random.default_rng(5)
+    for i in sorted(rng.choice(len(probs), size=8, replace=False)):
+        prob, u0 = probs[i], inits[i]
+        assert abs(dts[i] - orc.cfl_dt(prob, u0)) <= 1e-14 * dts[i]
+        check_sampled(orc, prob, u0, outs[i], float(dts[i]), picks_for(prob, int(i), 1), TOL["fp32"],
+                      f"problem {i} N={prob.N} nel={prob.nel[0]}")
