@@ -233,11 +233,30 @@ struct PredLds {
 
 // Threads per workgroup of the predictor: the number of lines of one axis
 // phase (n^D) rounded up to whole wavefronts, times a tuning factor (1 or
-// 2), at most 256.
+// 2), at most 256.  Factor kSplitLines (elasticity): two threads per line,
+// one for the velocity rows and one for the stress rows of the right-hand
+// side, each half of the block n^D rounded up to whole wavefronts.
+constexpr int kSplitLines = 4;
+__host__ __device__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
-  return (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > 256
-             ? 256
-             : (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor;
+  return factor == kSplitLines
+             ? 2 * round64(ipow(N + 1, D))
+             : ((ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > 256
+                    ? 256
+                    : (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor);
+}
+
+// Rows of the elastic right-hand side along axis A that one line task
+// computes: kPart 0 all of them; 1 the velocity rows, which need only the
+// gradients of the three stress components sig(i, A); 2 the stress rows,
+// which need only the velocity gradients.
+template <class PDE, int A, int kPart>
+__device__ __forceinline__ constexpr bool part_reads(int v) {
+  return kPart == 0 || (kPart == 1 ? (v == sig(0, A) || v == sig(1, A) || v == sig(2, A)) : v < 3);
+}
+template <int kPart>
+__device__ __forceinline__ constexpr bool part_writes(int v) {
+  return kPart == 0 || (kPart == 1 ? v < 3 : v >= 3);
 }
 
 template <typename T>
@@ -260,21 +279,23 @@ __device__ __forceinline__ float round_bf16(float x) {
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
 // With kAcc the result is added to the values already in sacc, else it is
 // stored.  With kRoundBF the contraction inputs are rounded to bfloat16.
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc>
+// kPart (elasticity only) restricts the line to one row group.
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0>
 __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu) {
   constexpr int n = N + 1, M = PDE::M;
   constexpr int ST = ipow(n, A);
+  static_assert(kPart == 0 || PDE::kElastic, "row groups are an elasticity split");
   T qv[n][M];
 #pragma unroll
   for (int j = 0; j < n; j++)
 #pragma unroll
-    for (int v = 0; v < M; v++) qv[j][v] = (T)sq[v * VS + base + j * ST];
+    for (int v = 0; v < M; v++) qv[j][v] = part_reads<PDE, A, kPart>(v) ? (T)sq[v * VS + base + j * ST] : T(0);
   // the accumulated right-hand side of the earlier axes
   T acc[n][M];
 #pragma unroll
   for (int k = 0; k < n; k++)
 #pragma unroll
-    for (int v = 0; v < M; v++) acc[k][v] = kAcc ? sacc[v * VS + base + k * ST] : T(0);
+    for (int v = 0; v < M; v++) acc[k][v] = (kAcc && part_writes<kPart>(v)) ? sacc[v * VS + base + k * ST] : T(0);
   if constexpr (!PDE::kElastic) {
     T F[n][M];
 #pragma unroll
@@ -314,21 +335,39 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
 #pragma unroll
   for (int k = 0; k < n; k++)
 #pragma unroll
-    for (int v = 0; v < M; v++) sacc[v * VS + base + k * ST] = acc[k][v];
+    for (int v = 0; v < M; v++)
+      if (part_writes<kPart>(v)) sacc[v * VS + base + k * ST] = acc[k][v];
 }
 
 // Right-hand side along axis A for all lines of the space-time element
 // (one thread per line, lines enumerated over (l0, the other spatial
 // indices)), accumulated onto the earlier axes (A > 0).
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS>
+// With kSplit (elasticity, BS = 2 * round64(lines)) the first half of the
+// block takes the velocity rows of every line and the second half the
+// stress rows (whole wavefronts on each side).
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kSplit = false>
 __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
   constexpr int ST = ipow(n, A);
-  for (int L = threadIdx.x; L < NST / n; L += BS) {
-    const int l0 = L / NF, r = L - l0 * NF;
-    const int base = l0 * ND + r % ST + (r / ST) * ST * n;
-    line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0)>(P, sq, sacc, base, irho, lam, mu);
+  if constexpr (kSplit) {
+    constexpr int H = round64(NST / n);
+    static_assert(BS == 2 * H && PDE::kElastic, "two threads per line");
+    const int half = threadIdx.x / H, L = threadIdx.x - half * H;
+    if (L < NST / n) {
+      const int l0 = L / NF, r = L - l0 * NF;
+      const int base = l0 * ND + r % ST + (r / ST) * ST * n;
+      if (half == 0)
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0), 1>(P, sq, sacc, base, irho, lam, mu);
+      else
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0), 2>(P, sq, sacc, base, irho, lam, mu);
+    }
+  } else {
+    for (int L = threadIdx.x; L < NST / n; L += BS) {
+      const int l0 = L / NF, r = L - l0 * NF;
+      const int base = l0 * ND + r % ST + (r / ST) * ST * n;
+      line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0)>(P, sq, sacc, base, irho, lam, mu);
+    }
   }
 }
 
@@ -336,24 +375,45 @@ __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho,
 // time slice, all axes at once: wavefront W takes the lines of axis W (and
 // W + BS/64, ...), one lane per line (n^(D-1) <= 64 lines per axis), and
 // stores that axis's contribution in part[A][M][ND]; the sum over A is left
-// to the consumer.
-template <int D, int N, class PDE, typename T, bool kRoundBF, int BS>
+// to the consumer.  With kSplit (elasticity) the tasks are (axis, row
+// group) pairs, wavefront W taking task W, W + BS/64, ...
+template <int D, int N, class PDE, int A, typename T, bool kRoundBF, int kPart>
+__device__ __forceinline__ void slice_lines(PArg &P, const T *w, T *part, int L, T irho, T lam, T mu) {
+  constexpr int n = N + 1, M = PDE::M, ND = ipow(n, D);
+  constexpr int ST = ipow(n, A);
+  const int base = L % ST + (L / ST) * ST * n;
+  line_rhs<D, N, PDE, A, T, T, kRoundBF, ND, false, kPart>(P, w, part + A * M * ND, base, irho, lam, mu);
+}
+
+template <int D, int N, class PDE, int A, typename T, bool kRoundBF, bool kSplit>
+__device__ __forceinline__ void slice_task(PArg &P, const T *w, T *part, int L, int g, T irho, T lam, T mu) {
+  if constexpr (kSplit) {
+    if (g == 1)
+      slice_lines<D, N, PDE, A, T, kRoundBF, 1>(P, w, part, L, irho, lam, mu);
+    else
+      slice_lines<D, N, PDE, A, T, kRoundBF, 2>(P, w, part, L, irho, lam, mu);
+  } else {
+    slice_lines<D, N, PDE, A, T, kRoundBF, 0>(P, w, part, L, irho, lam, mu);
+  }
+}
+
+template <int D, int N, class PDE, typename T, bool kRoundBF, int BS, bool kSplit = false>
 __device__ __forceinline__ void rhs_slice(PArg &P, const T *w, T *part, T irho, T lam, T mu) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
+  constexpr int NF = S::NF;
   static_assert(NF <= 64, "one wavefront per axis");
+  constexpr int NT = kSplit ? 2 * D : D;  // tasks
   const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
-  for (int A = wave; A < D; A += BS / 64) {
+  for (int t = wave; t < NT; t += BS / 64) {
     if (L < NF) {
+      const int A = kSplit ? t >> 1 : t;
+      const int g = kSplit ? 1 + (t & 1) : 0;
       if (A == 0) {
-        line_rhs<D, N, PDE, 0, T, T, kRoundBF, ND, false>(P, w, part, L * n, irho, lam, mu);
+        slice_task<D, N, PDE, 0, T, kRoundBF, kSplit>(P, w, part, L, g, irho, lam, mu);
       } else if (A == 1) {
-        if constexpr (D > 1)
-          line_rhs<D, N, PDE, 1, T, T, kRoundBF, ND, false>(P, w, part + M * ND, L % n + (L / n) * n * n, irho,
-                                                            lam, mu);
+        if constexpr (D > 1) slice_task<D, N, PDE, 1, T, kRoundBF, kSplit>(P, w, part, L, g, irho, lam, mu);
       } else {
-        if constexpr (D > 2)
-          line_rhs<D, N, PDE, 2, T, T, kRoundBF, ND, false>(P, w, part + 2 * M * ND, L, irho, lam, mu);
+        if constexpr (D > 2) slice_task<D, N, PDE, 2, T, kRoundBF, kSplit>(P, w, part, L, g, irho, lam, mu);
       }
     }
   }
@@ -425,17 +485,17 @@ __device__ __forceinline__ void gather_parts(const T *part, T (&out)[TimeItems<D
 }
 
 // One Picard sweep: R(q) over all axes, then the time contraction.
-template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS>
+template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false>
 __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu) {
-  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
   if constexpr (D > 1) {
-    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
   if constexpr (D > 2) {
-    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
   time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
@@ -448,13 +508,13 @@ __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO 
 // reduces to its row sums -- the same values as a full sweep up to rounding.
 // The sums are taken into registers before any write, so qout may overlap
 // `part`.
-template <int D, int N, class PDE, typename T, typename TO, bool kRoundBF, int BS>
+template <int D, int N, class PDE, typename T, typename TO, bool kRoundBF, int BS, bool kSplit = false>
 __device__ __forceinline__ void first_sweep(PArg &P, const T *w, T *part, TO *qout, const double *ureg, T dt,
                                             T irho, T lam, T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NU = TimeItems<D, N, M, BS>::value;
-  rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, w, part, irho, lam, mu);
+  rhs_slice<D, N, PDE, T, kRoundBF, BS, kSplit>(P, w, part, irho, lam, mu);
   __syncthreads();
   T r0[NU];
   gather_parts<D, N, PDE, T, BS>(part, r0);
@@ -486,13 +546,13 @@ __device__ __forceinline__ float opXi<float>(PArg &P, int l) { return cload(&P.s
 // On entry sq holds u in the compact [M][ND] layout, on exit the guess in
 // the space-time layout [M][n][ND]; sk is scratch for D M ND values that
 // does not overlap sq.
-template <int D, int N, class PDE, typename T, bool kRoundBF, int BS>
+template <int D, int N, class PDE, typename T, bool kRoundBF, int BS, bool kSplit = false>
 __device__ __forceinline__ void initial_guess(PArg &P, T *sq, T *sk, const double *ureg, T dt, T irho, T lam,
                                               T mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NU = TimeItems<D, N, M, BS>::value;
-  rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, sq, sk, irho, lam, mu);
+  rhs_slice<D, N, PDE, T, kRoundBF, BS, kSplit>(P, sq, sk, irho, lam, mu);
   __syncthreads();
   T k1[NU], c2[NU];
   gather_parts<D, N, PDE, T, BS>(sk, k1);
@@ -504,7 +564,7 @@ __device__ __forceinline__ void initial_guess(PArg &P, T *sq, T *sk, const doubl
       if (i < M * ND) sq[i] = (T)ureg[r] + dt * k1[r];
     }
     __syncthreads();
-    rhs_slice<D, N, PDE, T, kRoundBF, BS>(P, sq, sk, irho, lam, mu);
+    rhs_slice<D, N, PDE, T, kRoundBF, BS, kSplit>(P, sq, sk, irho, lam, mu);
     __syncthreads();
     gather_parts<D, N, PDE, T, BS>(sk, c2);
 #pragma unroll
@@ -768,41 +828,65 @@ __device__ __forceinline__ void ustar_update(const double *V, const double *ureg
 
 // Elastic volume term (one thread per node), fused with u* = u + dt V:
 //   V = -sum_A (1/h_A) B_A Dhat_A qbar,  qbar = sum_l0 w_l0 q(l0)  (B constant in the element)
-template <int D, int N, int BS>
+// Rows of row group kPart (part_writes) from the gradients they need
+// (part_reads).
+template <int D, int N, int kPart>
+__device__ __forceinline__ void elastic_volume_node(PArg &P, const double *QB, const double *ue, double *us,
+                                                    int k, double dt, double irho, double lam, double mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = 9, ND = S::ND;
+  double V[M];
+#pragma unroll
+  for (int v = 0; v < M; v++) V[v] = 0.0;
+  auto axis = [&](auto Ac) {
+    constexpr int A = decltype(Ac)::value;
+    constexpr int st = ipow(n, A);
+    const int ka = (k / st) % n;
+    const double *base = QB + (k - ka * st);
+    double g[M], bg[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      double s = 0.0;
+      if (part_reads<Elastic, A, kPart>(v))
+#pragma unroll
+        for (int j = 0; j < n; j++) s += cload(&P.ops->D[ka * kMaxN + j]) * base[v * ND + j * st];
+      g[v] = s;
+    }
+    elastic_bg<A, double>(g, irho, lam, mu, bg);
+#pragma unroll
+    for (int v = 0; v < M; v++) V[v] -= bg[v] * P.g.inv_h[A];
+  };
+  axis(std::integral_constant<int, 0>{});
+  axis(std::integral_constant<int, 1>{});
+  axis(std::integral_constant<int, 2>{});
+#pragma unroll
+  for (int v = 0; v < M; v++) {
+    if (!part_writes<kPart>(v)) continue;
+    const int i = v * ND + k;
+    us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V[v];
+  }
+}
+
+// All nodes of the element: one thread per node, or with kSplit (BS = 2 *
+// round64(n^D)) the velocity rows on the first half of the block and the
+// stress rows on the second.
+template <int D, int N, int BS, bool kSplit = false>
 __device__ __forceinline__ void elastic_volume_update(PArg &P, const double *QB, const double *ue,
                                                       double *us, double dt, double irho, double lam,
                                                       double mu) {
-  using S = Shape<D, N>;
-  constexpr int n = S::n, M = 9, ND = S::ND;
-  for (int k = threadIdx.x; k < ND; k += BS) {
-    double V[M];
-#pragma unroll
-    for (int v = 0; v < M; v++) V[v] = 0.0;
-    auto axis = [&](auto Ac) {
-      constexpr int A = decltype(Ac)::value;
-      constexpr int st = ipow(n, A);
-      const int ka = (k / st) % n;
-      const double *base = QB + (k - ka * st);
-      double g[M], bg[M];
-#pragma unroll
-      for (int v = 0; v < M; v++) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < n; j++) s += cload(&P.ops->D[ka * kMaxN + j]) * base[v * ND + j * st];
-        g[v] = s;
-      }
-      elastic_bg<A, double>(g, irho, lam, mu, bg);
-#pragma unroll
-      for (int v = 0; v < M; v++) V[v] -= bg[v] * P.g.inv_h[A];
-    };
-    axis(std::integral_constant<int, 0>{});
-    axis(std::integral_constant<int, 1>{});
-    axis(std::integral_constant<int, 2>{});
-#pragma unroll
-    for (int v = 0; v < M; v++) {
-      const int i = v * ND + k;
-      us[i] = dt == 0.0 ? ue[i] : ue[i] + dt * V[v];
+  constexpr int ND = Shape<D, N>::ND;
+  if constexpr (kSplit) {
+    constexpr int H = round64(ND);
+    static_assert(BS == 2 * H, "two threads per node");
+    const int half = threadIdx.x / H, k = threadIdx.x - half * H;
+    if (k < ND) {
+      if (half == 0)
+        elastic_volume_node<D, N, 1>(P, QB, ue, us, k, dt, irho, lam, mu);
+      else
+        elastic_volume_node<D, N, 2>(P, QB, ue, us, k, dt, irho, lam, mu);
     }
+  } else {
+    for (int k = threadIdx.x; k < ND; k += BS) elastic_volume_node<D, N, 0>(P, QB, ue, us, k, dt, irho, lam, mu);
   }
 }
 
@@ -906,7 +990,7 @@ __device__ __forceinline__ void traces_avg(PArg &P, const double *qf, const doub
 // Predictor outputs from the final FP64 iterate qf: optional qhat copy, the
 // face traces, the volume terms (scratch of D*M*ND doubles) and
 // u* = u + dt V.
-template <int D, int N, class PDE, typename TT, int BS>
+template <int D, int N, class PDE, typename TT, int BS, bool kSplit = false>
 __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, double *scratch,
                                                   const double *ue, const double *ureg, double dt, int64_t e,
                                                   double *qo, double irho, double lam, double mu) {
@@ -957,7 +1041,7 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
     if constexpr (N == 0) {
       for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
     } else {
-      elastic_volume_update<D, N, BS>(P, scratch, ue, us, dt, irho, lam, mu);
+      elastic_volume_update<D, N, BS, kSplit>(P, scratch, ue, us, dt, irho, lam, mu);
     }
   }
 }
@@ -983,11 +1067,14 @@ __device__ __forceinline__ void stage_slice0(TQ *sq, const double *ureg) {
 //    A), the last sweep in FP64 from that copy; its iterate lands in region
 //    R and feeds the FP64 outputs; traces are stored in FP32.
 //  kMfma: the FP32 sweeps contract on MFMA instead of VALU FMAs.
-//  kBFac: block-size factor (threads = pred_block(D, N, kBFac)).
+//  kBFac: block-size factor (threads = pred_block(D, N, kBFac)); kSplitLines
+//    splits every line of the Picard sweeps into its two elastic row groups.
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
 __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const double *ue, double dt,
                                                   double *qo, unsigned char *smem_raw) {
   constexpr int BS = pred_block(D, N, kBFac);
+  constexpr bool kSplit = kBFac == kSplitLines;
+  static_assert(!kSplit || (PDE::kElastic && !kMfma), "row-group split: elasticity, VALU sweeps");
   using S = Shape<D, N>;
   using L = PredLds<D, N, PDE::M, PREC>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
@@ -1014,14 +1101,14 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     int full = P.sweeps;  // sweeps over all time slices
     if (P.guess == 0) {
       // the first sweep starts from the time-constant iterate q^0 = u
-      first_sweep<D, N, PDE, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+      first_sweep<D, N, PDE, double, double, false, BS, kSplit>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
       full -= 1;
     } else {
-      initial_guess<D, N, PDE, double, false, BS>(P, sq, sacc, ureg, dt, irho, lam, mu);
+      initial_guess<D, N, PDE, double, false, BS, kSplit>(P, sq, sacc, ureg, dt, irho, lam, mu);
     }
     for (int s = 0; s < full; s++)
-      picard_sweep<D, N, PDE, double, double, double, false, BS>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, double, BS>(P, sq, sacc, ue, ureg, dt, e, qo, irho, lam, mu);
+      picard_sweep<D, N, PDE, double, double, double, false, BS, kSplit>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+    predictor_outputs<D, N, PDE, double, BS, kSplit>(P, sq, sacc, ue, ureg, dt, e, qo, irho, lam, mu);
   } else {
     constexpr bool kBF = PREC == kBF16;
     float *sq32 = (float *)smem_raw;
@@ -1034,8 +1121,9 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
       double *su = (double *)smem_raw;
       stage_slice0<D, N, PDE, double, BS>(su, ureg);
       __syncthreads();
-      first_sweep<D, N, PDE, double, double, false, BS>(P, su, sR, sR, ureg, dt, irho, lam, mu);
-      predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
+      first_sweep<D, N, PDE, double, double, false, BS, kSplit>(P, su, sR, sR, ureg, dt, irho, lam, mu);
+      predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam,
+                                                      mu);
       return;
     }
     stage_slice0<D, N, PDE, float, BS>(sq32, ureg);
@@ -1045,11 +1133,12 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     int full32 = P.sweeps - 1;
     if (P.guess == 0) {
       // first sweep from the time-constant iterate q^0 = u
-      first_sweep<D, N, PDE, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho, (float)lam,
+      first_sweep<D, N, PDE, float, float, kBF, BS, kSplit>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho, (float)lam,
                                                     (float)mu);
       full32 -= 1;
     } else {
-      initial_guess<D, N, PDE, float, kBF, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu);
+      initial_guess<D, N, PDE, float, kBF, BS, kSplit>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam,
+                                                     (float)mu);
     }
     if constexpr (PREC == kFP32 && kMfma) {
       // per-lane A operands: operator rows k = 4c + (lane & 3)
@@ -1067,13 +1156,13 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
         picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
     } else {
       for (int s = 0; s < full32; s++)
-        picard_sweep<D, N, PDE, float, float, float, kBF, BS>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho,
-                                                          (float)lam, (float)mu);
+        picard_sweep<D, N, PDE, float, float, float, kBF, BS, kSplit>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                  (float)irho, (float)lam, (float)mu);
     }
     // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
     // the FP64 accumulator in place
-    picard_sweep<D, N, PDE, double, float, double, false, BS>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
-    predictor_outputs<D, N, PDE, float, BS>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
+    picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
+    predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
   }
 }
 

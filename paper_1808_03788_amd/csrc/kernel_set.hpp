@@ -15,7 +15,7 @@ struct PredVariant {
   const char *name = "";
 };
 
-constexpr int kMaxVariants = 12;
+constexpr int kMaxVariants = 16;
 
 struct KernelSet {
   PredVariant pred[kMaxVariants];
@@ -58,6 +58,12 @@ KernelSet make_kernel_set() {
   add_variant<D, N, PDE, kFP32, true, true, 2>(k, "fp32-mfma-b2");
   add_variant<D, N, PDE, kBF16, true, false, 1>(k, "bf16-valu-b1");
   add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
+  if constexpr (PDE::kElastic && D == 3) {
+    add_variant<D, N, PDE, kFP64, true, false, kSplitLines>(k, "fp64-valu-split");
+    add_variant<D, N, PDE, kFP64, false, false, kSplitLines>(k, "fp64-valu-hbmacc-split");
+    add_variant<D, N, PDE, kFP32, true, false, kSplitLines>(k, "fp32-valu-split");
+    add_variant<D, N, PDE, kBF16, true, false, kSplitLines>(k, "bf16-valu-split");
+  }
   k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double, double>;
   k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float, float>;
   k.faceavg64[0] = (const void *)&k_face_avg<D, N, PDE, 0, double, double>;

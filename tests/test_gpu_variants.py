@@ -2,7 +2,9 @@
 
 The autotuner picks one implementation per kernel class by timing, so any
 variant can end up on the path.  Here each one is forced (ADER_VARIANT, read
-at ader_create) on 3-D Euler for N = 2..7 and elasticity for N = 2..5 and
+at ader_create) on 3-D Euler for N = 2..7 and elasticity for N = 2..5 (the
+split variants, two threads per line by elastic row group, exist for
+elasticity only) and
 held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-2
 (relative L2 after three steps).  A variant that does not fit the problem's
 LDS budget is not offered by the library and the case is skipped.
@@ -17,9 +19,9 @@ from paper_1808_03788_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 VARIANTS = {
-    "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1"],
-    "fp32": ["fp32-valu-b1", "fp32-valu-b2", "fp32-mfma-b1", "fp32-mfma-b2"],
-    "bf16": ["bf16-valu-b1", "bf16-valu-b2"],
+    "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1", "fp64-valu-split", "fp64-valu-hbmacc-split"],
+    "fp32": ["fp32-valu-b1", "fp32-valu-b2", "fp32-mfma-b1", "fp32-mfma-b2", "fp32-valu-split"],
+    "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-valu-split"],
 }
 TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
 CASES = [(pde, N, prec, v) for pde, Ns in (("euler", range(2, 8)), ("elastic", range(2, 6)))
