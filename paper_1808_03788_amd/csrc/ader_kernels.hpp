@@ -233,16 +233,20 @@ struct PredLds {
 
 // Threads per workgroup of the predictor: the number of lines of one axis
 // phase (n^D) rounded up to whole wavefronts, times a tuning factor (1 or
-// 2), at most 256.  Factor kSplitLines (elasticity): two threads per line,
-// one for the velocity rows and one for the stress rows of the right-hand
-// side, each half of the block n^D rounded up to whole wavefronts.
+// 2), at most 256, or 512 when a phase has more than 256 lines (one line
+// per thread with factor 2; these elements fill most of the LDS, so a
+// single workgroup per CU needs the larger block).  Factor kSplitLines
+// (elasticity): two threads per line, one for the velocity rows and one for
+// the stress rows of the right-hand side, each half of the block n^D
+// rounded up to whole wavefronts.
 constexpr int kSplitLines = 4;
 __host__ __device__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+__host__ __device__ constexpr int pred_block_cap(int D, int N) { return ipow(N + 1, D) > 256 ? 512 : 256; }
 __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
   return factor == kSplitLines
              ? 2 * round64(ipow(N + 1, D))
-             : ((ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > 256
-                    ? 256
+             : ((ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > pred_block_cap(D, N)
+                    ? pred_block_cap(D, N)
                     : (ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor);
 }
 
