@@ -161,14 +161,33 @@ def cpu_baseline(workload: str = "density", seconds: float = 12.0, guess: int = 
         if el >= seconds or steps >= 50:
             break
     dofs = sum(p.E * p.nd for p in probs)
-    return {
+    cores = oracle.num_threads()
+    out = {
         "value": dofs * steps / el,
         "unit": "DOF-updates/s",
-        "cores": oracle.num_threads(),
+        "cores": cores,
         "kind": "oracle",
         "sample": f"{what}, N={probs[0].N if len(probs) == 1 else 'mixed'}, {steps} steps, {el:.1f} s, "
                   f"plain C -O2 FP64 with OpenMP over elements",
     }
+    if workload != "batched":
+        # cost per DOF update on one core (the paper's TDU), on a 6^3 mesh of the same recipe
+        p1, u1, _ = make_workload(workload, "fp64", I, nel=6, guess=guess, face_avg=face_avg)
+        oracle.set_threads(1)
+        try:
+            t1, n1, t0 = 0.0, 0, time.perf_counter()
+            while True:
+                u1[0], t1, _ = oracle.step(p1[0], u1[0], t1, 1e9)
+                n1 += 1
+                el1 = time.perf_counter() - t0
+                if el1 >= seconds / 4 or n1 >= 20:
+                    break
+        finally:
+            oracle.set_threads(cores)
+        out["tdu_1thread_us"] = el1 / (n1 * p1[0].E * p1[0].nd) * 1e6
+        out["tdu_sample"] = (f"6^3 elements, N={p1[0].N}, {n1} steps on one thread, {el1:.1f} s; the paper's "
+                             f"TDU is 0.25 us for N=3 Euler with an initial guess and AVX-512 on one Skylake core")
+    return out
 
 
 def note(msg):
@@ -265,15 +284,17 @@ def run_path(workload, prec, steps, warmup, I, ader, torch, nel=None, degree=Non
                 value=dofs * steps * per_step / elapsed)
 
 
-def rel_l2_gpu(probs, a, b, I):
-    """max over problems and variables of the discrete L2 norm of a-b
-    relative to b (states of all problems concatenated).  The device only
-    reduces each element's nodes (one short contiguous sum per element and
-    variable); the sums over elements are finished on the host in FP64, so
-    no multi-workgroup device reduction is involved."""
+def errors_gpu(probs, a, b, I):
+    """Per variable, max over problems: the discrete L2 norm of a-b relative
+    to that of b, and max |a-b| relative to max |b| (states of all problems
+    concatenated).  The device only reduces each element's nodes (one short
+    contiguous reduction per element and variable); the reductions over
+    elements are finished on the host in FP64, so no multi-workgroup device
+    reduction is involved."""
     import numpy as np
     import torch
-    worst, off = 0.0, 0
+    l2 = linf = None
+    off = 0
     for prob in probs:
         cnt = prob.E * prob.m * prob.nd
         W = torch.tensor(I.quad_weights(prob), device=a.device)
@@ -281,9 +302,19 @@ def rel_l2_gpu(probs, a, b, I):
         b3 = b[off:off + cnt].view(prob.E, prob.m, prob.nd)
         num = ((a3 - b3) ** 2 * W).sum(dim=2).cpu().numpy().sum(axis=0)
         den = (b3 ** 2 * W).sum(dim=2).cpu().numpy().sum(axis=0)
-        worst = max(worst, float(np.max(np.sqrt(num) / np.sqrt(den))))
+        dmax = (a3 - b3).abs().amax(dim=2).cpu().numpy().max(axis=0)
+        bmax = b3.abs().amax(dim=2).cpu().numpy().max(axis=0)
+        e2, ei = np.sqrt(num) / np.sqrt(den), dmax / bmax
+        l2 = e2 if l2 is None else np.maximum(l2, e2)
+        linf = ei if linf is None else np.maximum(linf, ei)
         off += cnt
-    return worst
+    return [float(x) for x in l2], [float(x) for x in linf]
+
+
+def rel_l2_gpu(probs, a, b, I):
+    """max over problems and variables of the relative discrete L2 error
+    (errors_gpu)."""
+    return max(errors_gpu(probs, a, b, I)[0])
 
 
 def stage_summary(res, trace_bytes):
@@ -340,7 +371,11 @@ def main():
     head = ref if args.prec == "fp64" else run_path(args.workload, args.prec, args.steps, args.warmup, I,
                                                     ader, torch, **kw)
     probs = head["probs"]
-    err = 0.0 if head is ref else rel_l2_gpu(probs, head["u"], ref["u"], I)
+    if head is ref:
+        err_l2 = err_inf = [0.0] * probs[0].m
+    else:
+        err_l2, err_inf = errors_gpu(probs, head["u"], ref["u"], I)
+    err = max(err_l2)
     finite = head["finite"]
 
     flops = sum(predictor_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic", guess=p.guess) * p.E
@@ -402,7 +437,10 @@ def main():
             "kernels": ref["kernels"],
         },
         "speedup_vs_fp64": head["value"] / ref["value"],
+        "value_times_m": head["value"] * prob.m,
         "rel_l2_vs_fp64_path": err,
+        "rel_l2_per_variable": err_l2,
+        "rel_linf_per_variable": err_inf,
         "error_note": "max over problems and variables of the relative discrete L2 difference to "
                       "the FP64 GPU path after the same warmup+steps from the same state; the FP64 "
                       "path matches the FP64 oracle to <= 1e-12 (GPU parity tests)",

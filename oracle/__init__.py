@@ -70,6 +70,8 @@ def lib():
         L.orc_step.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP]
         L.orc_totals.argtypes = [C.POINTER(_Problem), _DP, _DP]
         L.orc_detect.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_void_p]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -225,3 +227,8 @@ def totals(prob, u: np.ndarray) -> np.ndarray:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's OpenMP loops (for timing)."""
+    lib().orc_set_threads(int(n))

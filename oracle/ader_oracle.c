@@ -34,6 +34,15 @@ int orc_num_threads(void) {
 #endif
 }
 
+/* Thread count of the OpenMP loops (timing of the oracle only). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ */
 /* 1-D basis (Sec. 2.1, paragraph after eq. ansatz.uh): Lagrange        */
 /* polynomials through the N+1 Gauss-Legendre nodes of [0,1].           */

@@ -116,6 +116,7 @@ int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *d
 int orc_totals(const orc_problem *p, const double *u, double *sums);
 /* Threads the OpenMP runtime will use. */
 int orc_num_threads(void);
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }
