@@ -317,6 +317,26 @@ def rel_l2_gpu(probs, a, b, I):
     return max(errors_gpu(probs, a, b, I)[0])
 
 
+def exact_errors(prec, steps, I, ader, torch, nel=None, degree=None):
+    """The noise-free twin of the density-wave workload (an exact solution:
+    the initial density profile translated with v = (1,1,1)): `steps` steps
+    of one precision mode from t = 0, then the per-variable relative L2 and
+    Linf errors against the exact state at the reached time."""
+    prob = I.density_wave_problem(nel=nel or 64, N=4 if degree is None else degree, prec=prec)
+    ctx = ader.Context([prob])
+    try:
+        u = ctx.upload([I.density_wave(prob, noise=0.0)])
+        for _ in range(steps):
+            ctx.step(u, [1e9])
+        torch.cuda.synchronize()
+        t = float(ctx.time()[0])
+        ex = ctx.upload([I.density_wave(prob, t=t, noise=0.0)])
+        l2, linf = errors_gpu([prob], u, ex, I)
+    finally:
+        ctx.close()
+    return {"steps": steps, "t": t, "rel_l2_per_variable": l2, "rel_linf_per_variable": linf}
+
+
 def stage_summary(res, trace_bytes):
     out = {}
     for k, (ms, cnt) in res["stages"].items():
@@ -350,6 +370,8 @@ def main():
                     help="face integrals from time-averaged traces")
     ap.add_argument("--no-guess-run", action="store_true",
                     help="skip the second measurement with the third-order initial guess")
+    ap.add_argument("--no-exact", action="store_true",
+                    help="skip the error of the noise-free twin against the exact solution")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device copy (calibrates HBM byte counters)")
@@ -481,6 +503,14 @@ def main():
                     "run with the same guess",
         }
         del ref2, head2
+    if args.workload == "density" and args.prec != "fp64" and not args.no_exact:
+        kwe = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree)
+        line["exact_solution_error"] = {
+            "note": "noise-free twin of the workload (the translated density wave is an exact solution), "
+                    "20 steps from t = 0 with the default sweeps and guess, each path against the exact state",
+            args.prec: exact_errors(args.prec, 20, I, ader, torch, **kwe),
+            "fp64": exact_errors("fp64", 20, I, ader, torch, **kwe),
+        }
     if args.calib_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
