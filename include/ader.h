@@ -203,8 +203,10 @@ ader_status ader_stage_times(ader_ctx *ctx, double *ms_host, int64_t *launches_h
  * (predictor variant, workgroup size, LDS bytes, how it was selected), as
  * a NUL-terminated string of at most len bytes in the host buffer buf.
  * The predictor variant is picked at ader_create: the implementations of
- * the problem's precision (VALU or MFMA contractions, two workgroup sizes)
- * are timed on a uniform state of up to 32768 elements and the fastest is
+ * the problem's precision that fit the LDS budget (VALU or MFMA
+ * contractions, two workgroup sizes; for elasticity also the variants with
+ * two threads per line, one per row group of the right-hand side) are
+ * timed on a uniform state of up to 32768 elements and the fastest is
  * kept, cached per configuration for the process.  Environment:
  * ADER_AUTOTUNE=0 keeps the first candidate; ADER_VARIANT=<name> forces one
  * (names as printed here). */
