@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
   static_assert(!kSplit || (PDE::kElastic && !kMfma), "row-group split: elasticity, VALU sweeps");
   using S = Shape<D, N>;
   using L = PredLds<D, N, PDE::M, PREC>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND;
   double irho = 0.0, lam = 0.0, mu = 0.0;
   if constexpr (PDE::kElastic) {
     irho = 1.0 / P.mat[3 * e + 0];
@@ -1227,7 +1227,7 @@ __device__ __forceinline__ void face_tile(const FaceArgs &F, int bx, int iy, int
   const int nx = F.g.nel[0], ny = F.g.nel[1], nz = F.g.nel[2];
   for (int it = threadIdx.x; it < NI; it += kBlock) {
     const int f = it / (n * NF), r = it - f * (n * NF);  // r = l0 * NF + kf
-    const int l0 = r / NF, kf = r - l0 * NF;
+    const int l0 = r / NF;
     const int ix = bx * FPB + f;
     if (ix >= nx) continue;
     const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);

@@ -82,7 +82,6 @@ struct ader_ctx {
   double *g_u = nullptr;
   int g_steps = 0;
   hipEvent_t g_in = nullptr, g_out = nullptr;
-  int ncu = 256;
   std::vector<ProbState> P;
   std::vector<KClass> K;
   double *dt = nullptr, *t = nullptr, *tnext = nullptr;  // device [nprob]
@@ -223,7 +222,7 @@ __global__ void __launch_bounds__(kBlock) k_totals_partial(const double *u, int6
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = kBlock / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
     if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + v] = red[0];
@@ -248,18 +247,6 @@ ader_status launch(ader_ctx *c, const void *fn, int64_t tiles, int grid, int thr
   if (grid < 1) return fail(c, ADER_ERR_UNSUPPORTED, "grid too large");
   HIP_OR_FAIL(c, hipLaunchKernel(fn, dim3((unsigned)grid), dim3(threads), args, shmem, c->cur));
   return ADER_OK;
-}
-
-// Persistent grid: as many workgroups as the device holds at once (at
-// least one), never more than there are tiles.
-int persistent_grid(ader_ctx *c, const void *fn, int threads, size_t shmem, int64_t tiles) {
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, threads, shmem) != hipSuccess || nb < 1) {
-    (void)hipGetLastError();
-    nb = 1;
-  }
-  const int64_t cap = (int64_t)nb * c->ncu;
-  return (int)(tiles < cap ? (tiles > 0 ? tiles : 1) : cap);
 }
 
 // Uniform state u[e][v][k] = val[v] (used to time predictor variants).
@@ -673,13 +660,6 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
     (void)hipGetLastError();
     c->msg = "no HIP device";
     return bail(ADER_ERR_DEVICE);
-  }
-  {
-    int ncu = 0;
-    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && ncu > 0)
-      c->ncu = ncu;
-    else
-      (void)hipGetLastError();
   }
   c->P.resize(nprob);
   int64_t uoff = 0, qoff = 0, moff = 0;
