@@ -50,7 +50,7 @@ struct RowTile {
   int p;     // problem within the launch's argument records
   int pidx;  // problem index in the context (its dt)
   int bx;    // chunk along the x-row
-  int yz;    // iy | iz << 16
+  uint32_t yz;  // iy | iz << 16 (each < 65536)
 };
 
 // The problem that owns `tile` (uniform: binary search on scalar loads).
@@ -1307,7 +1307,7 @@ __global__ void __launch_bounds__(kBlock) k_face(const FaceArgs *args, const Row
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const RowTile t = cload(&tiles[tile]);
     const FaceArgs F = cload(&args[t.p]);
-    face_tile<D, N, PDE, A, TT, GT>(F, t.bx, t.yz & 0xffff, t.yz >> 16, sD);
+    face_tile<D, N, PDE, A, TT, GT>(F, t.bx, (int)(t.yz & 0xffffu), (int)(t.yz >> 16), sD);
     __syncthreads();  // the next tile overwrites the LDS
   }
 }
@@ -1387,7 +1387,7 @@ __global__ void __launch_bounds__(kBlock) k_face_avg(const FaceArgs *args, const
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const RowTile t = cload(&tiles[tile]);
     const FaceArgs F = cload(&args[t.p]);
-    face_avg_tile<D, N, PDE, A, TT, GT>(F, t.bx, t.yz & 0xffff, t.yz >> 16);
+    face_avg_tile<D, N, PDE, A, TT, GT>(F, t.bx, (int)(t.yz & 0xffffu), (int)(t.yz >> 16));
   }
 }
 
@@ -1460,7 +1460,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const Ro
     const double d = cload(&dt[t.pidx]);
 #pragma unroll
     for (int c = 0; c < kUpdChunk; c++)
-      update_nodes<D, N, PDE, GT>(U, (t.bx * kUpdChunk + c) * kBlock + threadIdx.x, t.yz & 0xffff, t.yz >> 16, u, d);
+      update_nodes<D, N, PDE, GT>(U, (t.bx * kUpdChunk + c) * kBlock + threadIdx.x, (int)(t.yz & 0xffffu), (int)(t.yz >> 16), u, d);
   }
 }
 

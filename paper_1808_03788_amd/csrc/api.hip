@@ -430,8 +430,8 @@ ader_status build_class(ader_ctx *c, KClass &k) {
     cs[i + 1] = cs[i] + rows;
     for (int r = 0; r < rows; r++) {
       const int iy = r % s.g.nel[1], iz = r / s.g.nel[1];
-      for (int bx = 0; bx < fa[0][i].cx; bx++) ft.push_back(RowTile{i, p, bx, iy | iz << 16});
-      for (int bx = 0; bx < u.cx; bx++) ut.push_back(RowTile{i, p, bx, iy | iz << 16});
+      for (int bx = 0; bx < fa[0][i].cx; bx++) ft.push_back(RowTile{i, p, bx, (uint32_t)iy | (uint32_t)iz << 16});
+      for (int bx = 0; bx < u.cx; bx++) ut.push_back(RowTile{i, p, bx, (uint32_t)iy | (uint32_t)iz << 16});
     }
   }
   ader_status st;

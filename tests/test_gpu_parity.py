@@ -99,6 +99,49 @@ def test_every_degree_3d(A, orc, N):
     check(prob, ug, uo, what=f"N={N}")
 
 
+def _elastic_degenerate(prec):
+    p = I.Problem(dim=3, N=2, nel=(1, 2, 1), lo=(0, 0, 0), hi=(1, 1, 1), pde="elastic", prec=prec)
+    p.material = I.homogeneous_material(p)
+    return p
+
+
+# Meshes with a single element along some axis: the element is its own
+# neighbour across those faces (both traces of the face come from it).
+DEGENERATE = [
+    ("euler3d_N3_1x1x1", lambda prec: I.Problem(dim=3, N=3, nel=(1, 1, 1), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec),
+     lambda p: I.density_wave(p)),
+    ("euler3d_N2_1x3x2", lambda prec: I.Problem(dim=3, N=2, nel=(1, 3, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec),
+     lambda p: I.density_wave(p)),
+    ("euler2d_N3_1x1", lambda prec: I.Problem(dim=2, N=3, nel=(1, 1), lo=(0, 0), hi=(10, 10), prec=prec),
+     I.isentropic_vortex),
+    ("elastic_N2_1x2x1", _elastic_degenerate, lambda p: I.stress_pulse(p, width=0.3)),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,mk,init", DEGENERATE, ids=[c[0] for c in DEGENERATE])
+def test_single_element_axes(A, orc, name, mk, init, prec):
+    prob = mk(prec)
+    u0 = init(prob)
+    say(f"[parity] degenerate mesh {name} {prec}")
+    ug, _ = gpu_run(A, prob, u0, 3)
+    uo, _ = orc_run(orc, mk("fp64"), u0, 3)
+    check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec}")
+
+
+@pytest.mark.parametrize("nel", [(40000, 1, 1), (1, 40000, 1), (1, 1, 40000)],
+                         ids=["x40000", "y40000", "z40000"])
+def test_longest_axes(A, orc, nel):
+    """40000 elements along one axis (row indices above 2^15 are packed in
+    the face and update tiles)."""
+    prob = I.Problem(dim=3, N=1, nel=nel, lo=(0, 0, 0), hi=(1, 1, 1))
+    u0 = I.density_wave(prob)
+    say(f"[parity] long axis {nel}")
+    ug, _ = gpu_run(A, prob, u0, 2)
+    uo, _ = orc_run(orc, prob, u0, 2)
+    check(prob, ug, uo, what=f"nel={nel}")
+
+
 def test_predictor_qhat_parity(A, orc):
     import torch
     for prob, u0 in [
