@@ -67,8 +67,14 @@ typedef enum { ADER_FP64 = 0, ADER_FP32 = 1, ADER_BF16 = 2 } ader_prec;
 
 typedef struct {
   int32_t dim;          /* 2 or 3 (elasticity: 3) */
-  int32_t degree;       /* N in [0,7]; supported N depends on dim/pde/prec (LDS) */
-  int32_t nelem[3];     /* elements per axis, >= 1 (nelem[2] ignored for dim = 2) */
+  int32_t degree;       /* N in [0,7].  The space-time DOFs of one element must
+                           fit one CU's LDS (160 KB): 2-D Euler every N; 3-D
+                           Euler N <= 7 in FP64 (N >= 6 with the accumulator in
+                           HBM) and N <= 6 in FP32/BF16; elasticity N <= 5 (N = 5
+                           FP64 with the accumulator in HBM).  Other
+                           combinations: ADER_ERR_UNSUPPORTED at create. */
+  int32_t nelem[3];     /* elements per axis, 1..65535 (nelem[2] ignored for
+                           dim = 2) */
   double lo[3], hi[3];  /* box; periodic in every axis */
   int32_t pde;          /* ader_pde */
   double gamma;         /* Euler: ratio of specific heats (> 1) */

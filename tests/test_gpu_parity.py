@@ -142,6 +142,21 @@ def test_longest_axes(A, orc, nel):
     check(prob, ug, uo, what=f"nel={nel}")
 
 
+@pytest.mark.parametrize("name,mk", [
+    ("euler3d_N7_fp32", lambda: I.Problem(dim=3, N=7, nel=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec="fp32")),
+    ("euler3d_N7_bf16", lambda: I.Problem(dim=3, N=7, nel=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec="bf16")),
+    ("elastic_N6_fp64", lambda: I.elastic_problem(nel=2, N=6)),
+    ("elastic_N7_fp32", lambda: I.elastic_problem(nel=2, N=7, prec="fp32")),
+], ids=["euler3d_N7_fp32", "euler3d_N7_bf16", "elastic_N6_fp64", "elastic_N7_fp32"])
+def test_classes_beyond_lds_are_unsupported(A, name, mk):
+    """One element's space-time DOFs exceed the LDS of a CU: ader_create
+    refuses with UNSUPPORTED and says why."""
+    with pytest.raises(A.AderError) as e:
+        A.Context([mk()])
+    assert e.value.status == A.ADER_ERR_UNSUPPORTED, (name, e.value.status)
+    assert "LDS" in str(e.value)
+
+
 def test_predictor_qhat_parity(A, orc):
     import torch
     for prob, u0 in [
