@@ -229,6 +229,12 @@ struct PredLds {
   // (M * ACC doubles: the space-time accumulator or FP64 iterate, and at
   // least the D per-axis parts of a one-slice right-hand side)
   static constexpr size_t R = round256((size_t)M * S::ACC * 8);
+  // FP64 row-group sweeps (elasticity): q in region A, then the stress-row
+  // accumulator (M - 3 variables), which also holds the per-axis parts of a
+  // one-slice right-hand side and the output scratch
+  static constexpr size_t G = round256(
+      (size_t)(M - 3) * S::NST * 8 > (size_t)D * M * S::ND * 8 ? (size_t)(M - 3) * S::NST * 8
+                                                                : (size_t)D * M * S::ND * 8);
 };
 
 // Threads per workgroup of the predictor: the number of lines of one axis
@@ -240,10 +246,14 @@ struct PredLds {
 // the stress rows of the right-hand side, each half of the block n^D
 // rounded up to whole wavefronts.
 constexpr int kSplitLines = 4;
+// Factor kRowGroups (FP64 elasticity): one thread per line, the two row
+// groups of a sweep one after the other (elastic_group_sweep).
+constexpr int kRowGroups = 8;
 __host__ __device__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
 __host__ __device__ constexpr int pred_block_cap(int D, int N) { return ipow(N + 1, D) > 256 ? 512 : 256; }
 __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
-  return factor == kSplitLines
+  return factor == kRowGroups ? pred_block(D, N, 1)
+         : factor == kSplitLines
              ? 2 * round64(ipow(N + 1, D))
              : ((ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > pred_block_cap(D, N)
                     ? pred_block_cap(D, N)
@@ -283,8 +293,10 @@ __device__ __forceinline__ float round_bf16(float x) {
 //   R -= (1/h_A) B_A (Dhat_A q)          (elasticity)
 // With kAcc the result is added to the values already in sacc, else it is
 // stored.  With kRoundBF the contraction inputs are rounded to bfloat16.
-// kPart (elasticity only) restricts the line to one row group.
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0>
+// kPart (elasticity only) restricts the line to one row group; variable v
+// of the accumulator is held at (v - kAccShift) * VS.
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0,
+          int kAccShift = 0>
 __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu) {
   constexpr int n = N + 1, M = PDE::M;
   constexpr int ST = ipow(n, A);
@@ -299,7 +311,8 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
 #pragma unroll
   for (int k = 0; k < n; k++)
 #pragma unroll
-    for (int v = 0; v < M; v++) acc[k][v] = (kAcc && part_writes<kPart>(v)) ? sacc[v * VS + base + k * ST] : T(0);
+    for (int v = 0; v < M; v++)
+      acc[k][v] = (kAcc && part_writes<kPart>(v)) ? sacc[(v - kAccShift) * VS + base + k * ST] : T(0);
   if constexpr (!PDE::kElastic) {
     T F[n][M];
 #pragma unroll
@@ -340,7 +353,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
   for (int k = 0; k < n; k++)
 #pragma unroll
     for (int v = 0; v < M; v++)
-      if (part_writes<kPart>(v)) sacc[v * VS + base + k * ST] = acc[k][v];
+      if (part_writes<kPart>(v)) sacc[(v - kAccShift) * VS + base + k * ST] = acc[k][v];
 }
 
 // Right-hand side along axis A for all lines of the space-time element
@@ -503,6 +516,80 @@ __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO 
     __syncthreads();
   }
   time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
+  __syncthreads();
+}
+
+// Lines of axis A for one row group kPart, one thread per line, accumulator
+// variable v at (v - kShift) * NST of sacc.
+template <int D, int N, class PDE, int A, int kPart, int kShift, int BS>
+__device__ __forceinline__ void rhs_axis_group(PArg &P, const double *sq, double *sacc, double irho, double lam,
+                                               double mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int ST = ipow(n, A);
+  for (int L = threadIdx.x; L < NST / n; L += BS) {
+    const int l0 = L / NF, r = L - l0 * NF;
+    const int base = l0 * ND + r % ST + (r / ST) * ST * n;
+    line_rhs<D, N, PDE, A, double, double, false, NST, (A > 0), kPart, kShift>(P, sq, sacc, base, irho, lam, mu);
+  }
+}
+
+// Time contraction of the variables v0 <= v < v1 only: q(l0, k) = u(k) +
+// dt sum_j0 T[l0][j0] R(j0, k), R of variable v at (v - shift) * NST of
+// sacc, written to (v - shift) * NST of qout (same owners as time_phase).
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void time_phase_vars(PArg &P, const double *sacc, double *qout, int shift,
+                                                const double *ureg, double dt, int v0, int v1) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+#pragma unroll
+  for (int r = 0; r < NU; r++) {
+    const int i = threadIdx.x + r * BS;
+    const int v = i / ND, k = i - v * ND;
+    if (i < M * ND && v >= v0 && v < v1) {
+      double rr[n];
+#pragma unroll
+      for (int j = 0; j < n; j++) rr[j] = sacc[(v - shift) * NST + j * ND + k];
+#pragma unroll
+      for (int l = 0; l < n; l++) {
+        double a = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; j++) a += opT<double>(P, l * kMaxN + j) * rr[j];
+        qout[(v - shift) * NST + l * ND + k] = ureg[r] + dt * a;
+      }
+    }
+  }
+}
+
+// One FP64 elastic Picard sweep by row groups, in LDS q ([M][NST]) plus an
+// accumulator sS of the M-3 stress variables.  The stress rows need only
+// the velocity gradients and the velocity rows only the stress gradients,
+// so: (1) the stress rows into sS, time-contracted there; (2) the velocity
+// rows into the velocity slots of q (their old values are no longer read),
+// time-contracted in place, from the old stresses still in q; (3) the new
+// stresses copied into q.  Every row is a function of the previous iterate,
+// as in picard_sweep.
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void elastic_group_sweep(PArg &P, double *sq, double *sS, const double *ureg,
+                                                    double dt, double irho, double lam, double mu) {
+  static_assert(PDE::kElastic && D == 3, "row groups: 3-D elasticity");
+  constexpr int M = PDE::M, NST = Shape<D, N>::NST;
+  rhs_axis_group<D, N, PDE, 0, 2, 3, BS>(P, sq, sS, irho, lam, mu);
+  __syncthreads();
+  rhs_axis_group<D, N, PDE, 1, 2, 3, BS>(P, sq, sS, irho, lam, mu);
+  __syncthreads();
+  rhs_axis_group<D, N, PDE, 2, 2, 3, BS>(P, sq, sS, irho, lam, mu);
+  __syncthreads();
+  time_phase_vars<D, N, PDE, BS>(P, sS, sS, 3, ureg, dt, 3, M);
+  rhs_axis_group<D, N, PDE, 0, 1, 0, BS>(P, sq, sq, irho, lam, mu);
+  __syncthreads();
+  rhs_axis_group<D, N, PDE, 1, 1, 0, BS>(P, sq, sq, irho, lam, mu);
+  __syncthreads();
+  rhs_axis_group<D, N, PDE, 2, 1, 0, BS>(P, sq, sq, irho, lam, mu);
+  __syncthreads();
+  time_phase_vars<D, N, PDE, BS>(P, sq, sq, 0, ureg, dt, 0, 3);
+  for (int i = threadIdx.x; i < (M - 3) * NST; i += BS) sq[3 * NST + i] = sS[i];
   __syncthreads();
 }
 
@@ -1095,7 +1182,22 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     const int i = threadIdx.x + r * BS;
     ureg[r] = i < M * ND ? ue[i] : 0.0;
   }
-  if constexpr (PREC == kFP64) {
+  if constexpr (PREC == kFP64 && kBFac == kRowGroups) {
+    static_assert(PDE::kElastic && kAccLds && !kMfma, "row groups: FP64 elasticity, accumulator in LDS");
+    double *sq = (double *)smem_raw;
+    double *sS = (double *)(smem_raw + L::A);
+    stage_slice0<D, N, PDE, double, BS>(sq, ureg);
+    __syncthreads();
+    int full = P.sweeps;
+    if (P.guess == 0) {
+      first_sweep<D, N, PDE, double, double, false, BS>(P, sq, sS, sq, ureg, dt, irho, lam, mu);
+      full -= 1;
+    } else {
+      initial_guess<D, N, PDE, double, false, BS>(P, sq, sS, ureg, dt, irho, lam, mu);
+    }
+    for (int s = 0; s < full; s++) elastic_group_sweep<D, N, PDE, BS>(P, sq, sS, ureg, dt, irho, lam, mu);
+    predictor_outputs<D, N, PDE, double, BS>(P, sq, sS, ue, ureg, dt, e, qo, irho, lam, mu);
+  } else if constexpr (PREC == kFP64) {
     double *sq = (double *)smem_raw;
     double *sacc = kAccLds ? (double *)(smem_raw + L::A) : P.acc_glob + e * (int64_t)(M * S::ACC);
     // q^0 = u_h(t^n), constant in time (K1^{-1} F0 = 1): the first sweep

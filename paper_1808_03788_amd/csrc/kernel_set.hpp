@@ -37,7 +37,7 @@ void add_variant(KernelSet &k, const char *name) {
   PredVariant v;
   v.fn = (const void *)&k_predictor<D, N, PDE, PREC, kAccLds, kMfma, kBFac>;
   v.threads = pred_block(D, N, kBFac);
-  v.lds = (PREC == kFP64 && !kAccLds) ? L::A : L::A + L::R;
+  v.lds = (PREC == kFP64 && !kAccLds) ? L::A : (kBFac == kRowGroups ? L::A + L::G : L::A + L::R);
   v.prec = PREC;
   v.acc_lds = kAccLds;
   v.mfma = kMfma;
@@ -63,6 +63,7 @@ KernelSet make_kernel_set() {
     add_variant<D, N, PDE, kFP64, false, false, kSplitLines>(k, "fp64-valu-hbmacc-split");
     add_variant<D, N, PDE, kFP32, true, false, kSplitLines>(k, "fp32-valu-split");
     add_variant<D, N, PDE, kBF16, true, false, kSplitLines>(k, "bf16-valu-split");
+    add_variant<D, N, PDE, kFP64, true, false, kRowGroups>(k, "fp64-valu-groups");
   }
   k.face64[0] = (const void *)&k_face<D, N, PDE, 0, double, double>;
   k.face32[0] = (const void *)&k_face<D, N, PDE, 0, float, float>;

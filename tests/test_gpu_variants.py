@@ -19,7 +19,8 @@ from paper_1808_03788_amd import inputs as I
 pytestmark = pytest.mark.gpu
 
 VARIANTS = {
-    "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1", "fp64-valu-split", "fp64-valu-hbmacc-split"],
+    "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1", "fp64-valu-split", "fp64-valu-hbmacc-split",
+             "fp64-valu-groups"],
     "fp32": ["fp32-valu-b1", "fp32-valu-b2", "fp32-mfma-b1", "fp32-mfma-b2", "fp32-valu-split"],
     "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-valu-split"],
 }
