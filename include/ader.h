@@ -71,7 +71,7 @@ typedef struct {
                            fit one CU's LDS (160 KB): 2-D Euler every N; 3-D
                            Euler N <= 7 in FP64 (N >= 6 with the accumulator in
                            HBM) and N <= 6 in FP32/BF16; elasticity N <= 5 (N = 5
-                           FP64 with the accumulator in HBM).  Other
+                           FP64 by row groups).  Other
                            combinations: ADER_ERR_UNSUPPORTED at create. */
   int32_t nelem[3];     /* elements per axis, 1..65535 (nelem[2] ignored for
                            dim = 2) */
