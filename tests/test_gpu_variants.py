@@ -3,8 +3,8 @@
 The autotuner picks one implementation per kernel class by timing, so any
 variant can end up on the path.  Here each one is forced (ADER_VARIANT, read
 at ader_create) on 3-D Euler for N = 2..7 and elasticity for N = 2..5 (the
-split variants, two threads per line by elastic row group, exist for
-elasticity only) and
+split variants, two threads per line by elastic row group, and the FP64
+row-group sweep exist for elasticity only) and
 held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-2
 (relative L2 after three steps).  A variant that does not fit the problem's
 LDS budget is not offered by the library and the case is skipped.
