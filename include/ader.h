@@ -176,7 +176,8 @@ ader_status ader_run(ader_ctx *ctx, double *u, const double *t_end_host, int32_t
  * delta = max(1e-4, 1e-3 (M - m)).  Allocates 4 bytes per element and
  * 16 m bytes per element at the first enable; switching drops a captured
  * ader_run graph.  The detection time is counted in the update stage of
- * ader_stage_times. */
+ * ader_stage_times.  If enabling fails (ADER_ERR_OOM, ADER_ERR_DEVICE),
+ * detection stays off; buffers already allocated are kept for a later call. */
 ader_status ader_set_detection(ader_ctx *ctx, int32_t enable);
 /* Flags of the last detected step, host int32 [sum over problems of E],
  * problems in order, elements e = ix + nx (iy + ny iz) within a problem;

@@ -312,22 +312,31 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
           return ADER_OK;
         }
   }
-  double *ut = nullptr;
+  // the timing state, released on every return (hipFree waits for the launches)
+  struct Scratch {
+    double *ut = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Scratch() {
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+      if (ut) (void)hipFree(ut);
+    }
+  } sc;
   const int64_t cnt = Et * s.m * s.nd;
-  if (hipMalloc(&ut, cnt * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&sc.ut, cnt * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
+    sc.ut = nullptr;
     return ADER_OK;  // no room to tune: keep the default
   }
+  double *ut = sc.ut;
   PredArgs a = pred_args(s, pl);
   a.u_off = 0;
   const int64_t start[2] = {0, Et};
   PredArgs *a_dev = nullptr;
   int64_t *st_dev = nullptr;
   ader_status st;
-  if ((st = upload(c, (void **)&a_dev, &a, sizeof(a))) || (st = upload(c, (void **)&st_dev, start, sizeof(start)))) {
-    (void)hipFree(ut);
+  if ((st = upload(c, (void **)&a_dev, &a, sizeof(a))) || (st = upload(c, (void **)&st_dev, start, sizeof(start))))
     return st;
-  }
   const double ie = 1.0 / (s.desc.gamma - 1.0);  // Euler: rho = 1, v = 0, p = 1
   const unsigned nb = (unsigned)((cnt + 255) / 256);
   if (s.desc.pde == ADER_EULER)
@@ -338,9 +347,9 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
                        1.0, 1.0);
   const double dt_tune = 1e-6;
   HIP_OR_FAIL(c, hipMemcpyAsync(c->dt + pl, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->cur));
-  hipEvent_t e0, e1;
-  HIP_OR_FAIL(c, hipEventCreate(&e0));
-  HIP_OR_FAIL(c, hipEventCreate(&e1));
+  HIP_OR_FAIL(c, hipEventCreate(&sc.e0));
+  HIP_OR_FAIL(c, hipEventCreate(&sc.e1));
+  hipEvent_t e0 = sc.e0, e1 = sc.e1;
   Batch b{st_dev, 1};
   const double *dtp = c->dt;
   double *qn = nullptr;
@@ -363,10 +372,7 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
       bestv = v;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   HIP_OR_FAIL(c, hipStreamSynchronize(c->cur));
-  (void)hipFree(ut);
   if (st) return st;
   const double zero = 0.0;
   HIP_OR_FAIL(c, hipMemcpy(c->dt + pl, &zero, sizeof(double), hipMemcpyHostToDevice));
@@ -992,11 +998,13 @@ ader_status ader_set_detection(ader_ctx *c, int32_t enable) {
   const bool on = enable != 0;
   if (on == c->detect) return ADER_OK;
   ader_status st;
-  if (on && !c->flags) {
-    if ((st = dalloc(c, (void **)&c->flags, (size_t)c->total_e * sizeof(int)))) return st;
+  if (on) {  // buffers kept from an earlier call (also one that failed part-way) are reused
+    if (!c->flags) {
+      if ((st = dalloc(c, (void **)&c->flags, (size_t)c->total_e * sizeof(int)))) return st;
+      HIP_OR_FAIL(c, hipMemset(c->flags, 0, (size_t)c->total_e * sizeof(int)));
+    }
     for (ProbState &s : c->P)
-      if ((st = dalloc(c, (void **)&s.summ, (size_t)s.E * s.m * 2 * sizeof(double)))) return st;
-    HIP_OR_FAIL(c, hipMemset(c->flags, 0, (size_t)c->total_e * sizeof(int)));
+      if (!s.summ && (st = dalloc(c, (void **)&s.summ, (size_t)s.E * s.m * 2 * sizeof(double)))) return st;
   }
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
   if (c->gexec) {  // the captured steps no longer match
@@ -1006,7 +1014,12 @@ ader_status ader_set_detection(ader_ctx *c, int32_t enable) {
   }
   c->detect = on;
   for (KClass &k : c->K)
-    if ((st = refresh_detection(c, k))) return st;
+    if ((st = refresh_detection(c, k))) {
+      // incomplete records: leave detection off (steps then launch no detection kernel)
+      c->detect = false;
+      for (KClass &r : c->K) (void)refresh_detection(c, r);
+      return st;
+    }
   return ADER_OK;
 }
 
