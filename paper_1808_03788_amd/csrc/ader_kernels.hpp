@@ -459,8 +459,9 @@ __device__ __forceinline__ double opTrow<double>(PArg &P, int l) { return cload(
 template <>
 __device__ __forceinline__ float opTrow<float>(PArg &P, int l) { return cload(&P.sw->Trowf[l]); }
 
-template <int D, int N, class PDE, typename T, typename TO, int BS>
-__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout, const double *ureg, T dt) {
+template <int D, int N, class PDE, typename T, typename TO, int BS, bool kTwo = false>
+__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout, const double *ureg, T dt,
+                                           const T *sacc2 = nullptr) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NU = TimeItems<D, N, M, BS>::value;
@@ -472,7 +473,10 @@ __device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout, con
       const T u0 = (T)ureg[r];
       T rr[n];
 #pragma unroll
-      for (int j = 0; j < n; j++) rr[j] = sacc[v * NST + j * ND + k];
+      for (int j = 0; j < n; j++) {
+        rr[j] = sacc[v * NST + j * ND + k];
+        if constexpr (kTwo) rr[j] += sacc2[v * NST + j * ND + k];
+      }
 #pragma unroll
       for (int l = 0; l < n; l++) {
         T a = T(0);
@@ -501,10 +505,52 @@ __device__ __forceinline__ void gather_parts(const T *part, T (&out)[TimeItems<D
   }
 }
 
-// One Picard sweep: R(q) over all axes, then the time contraction.
-template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false>
+// Whether a block of BS threads holds the lines of two axes at once, each
+// set on its own half of whole wavefronts (one thread per line).
+template <int D, int N, int BS>
+__host__ __device__ constexpr bool pair_axes() {
+  return D >= 2 && BS >= 2 * round64(ipow(N + 1, D));
+}
+
+// Axes 0 and 1 at the same time: the first half of the block stores the
+// lines of axis 0 into sacc, the second half those of axis 1 into sacc2
+// (the time phase adds the two).
+template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS>
+__device__ __forceinline__ void rhs_axes01(PArg &P, const TQ *sq, T *sacc, T *sacc2, T irho, T lam, T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int H = round64(NST / n);
+  static_assert(pair_axes<D, N, BS>(), "two halves of whole wavefronts");
+  const int half = threadIdx.x / H, L = threadIdx.x - half * H;
+  if (L < NST / n) {
+    const int l0 = L / NF, r = L - l0 * NF;
+    if (half == 0)
+      line_rhs<D, N, PDE, 0, T, TQ, kRoundBF, NST, false>(P, sq, sacc, l0 * ND + r * n, irho, lam, mu);
+    else if (half == 1)
+      line_rhs<D, N, PDE, 1, T, TQ, kRoundBF, NST, false>(P, sq, sacc2, l0 * ND + r % n + (r / n) * n * n, irho,
+                                                          lam, mu);
+  }
+}
+
+// One Picard sweep: R(q) over all axes, then the time contraction.  With
+// kPair (pair_axes, a second accumulator sacc2 of M NST values) axes 0 and
+// 1 run at the same time and axis 2 then accumulates onto sacc.
+template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false,
+          bool kPair = false>
 __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
-                                             const double *ureg, T dt, T irho, T lam, T mu) {
+                                             const double *ureg, T dt, T irho, T lam, T mu, T *sacc2 = nullptr) {
+  if constexpr (kPair) {
+    static_assert(!kSplit, "one thread per line");
+    rhs_axes01<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
+    __syncthreads();
+    if constexpr (D > 2) {
+      rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+      __syncthreads();
+    }
+    time_phase<D, N, PDE, T, TO, BS, true>(P, sacc, qout, ureg, dt, sacc2);
+    __syncthreads();
+    return;
+  }
   rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
   if constexpr (D > 1) {
@@ -1260,6 +1306,14 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
         }
       for (int s = 0; s < full32; s++)
         picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
+    } else if constexpr (!kSplit && pair_axes<D, N, BS>()) {
+      // the FP32 accumulator fills half of region R: the second one takes the other half
+      static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");
+      float *sacc32b = sacc32 + M * S::NST;
+      for (int s = 0; s < full32; s++)
+        picard_sweep<D, N, PDE, float, float, float, kBF, BS, false, true>(P, sq32, sacc32, sq32, ureg, dtf,
+                                                                          (float)irho, (float)lam, (float)mu,
+                                                                          sacc32b);
     } else {
       for (int s = 0; s < full32; s++)
         picard_sweep<D, N, PDE, float, float, float, kBF, BS, kSplit>(P, sq32, sacc32, sq32, ureg, dtf,
