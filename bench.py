@@ -352,8 +352,9 @@ def stage_summary(res, trace_bytes):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=-1,
+                    help="timed steps (-1: 50, or 3 graph replays of 10 steps for the batched workload)")
+    ap.add_argument("--warmup", type=int, default=-1, help="warm-up steps (-1: 3, or 1 replay for batched)")
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "fp64"],
                     help="precision of the headline path (compared against fp64)")
     ap.add_argument("--workload", default="density", choices=["density", "elastic", "batched", "fourier"])
@@ -376,6 +377,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.steps < 0:
+        args.steps = 3 if args.workload == "batched" else 50
+    if args.warmup < 0:
+        args.warmup = 1 if args.workload == "batched" else 3
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; "
                                    "multi-GPU sharding is not built (--gpus 1)"}))
