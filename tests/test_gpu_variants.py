@@ -2,9 +2,11 @@
 
 The autotuner picks one implementation per kernel class by timing, so any
 variant can end up on the path.  Here each one is forced (ADER_VARIANT, read
-at ader_create) on 3-D Euler for N = 2..7 and elasticity for N = 2..5 (the
-split variants, two threads per line by elastic row group, and the FP64
-row-group sweep exist for elasticity only) and
+at ader_create) on 2-D and 3-D Euler for N = 1..7 and elasticity for
+N = 1..5 (the split variants, two threads per line by elastic row group,
+and the FP64 row-group sweep exist for elasticity only; the factor-2 FP32
+and BF16 variants run axes 0 and 1 at the same time wherever the block
+holds both sets of lines, which covers 2-D, and 3-D up to N = 4) and
 held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-2
 (relative L2 after three steps).  A variant that does not fit the problem's
 LDS budget is not offered by the library and the case is skipped.
@@ -25,7 +27,7 @@ VARIANTS = {
     "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-valu-split"],
 }
 TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
-CASES = [(pde, N, prec, v) for pde, Ns in (("euler", range(2, 8)), ("elastic", range(2, 6)))
+CASES = [(pde, N, prec, v) for pde, Ns in (("euler2", range(1, 8)), ("euler", range(1, 8)), ("elastic", range(1, 6)))
          for N in Ns for prec, vs in VARIANTS.items() for v in vs]
 
 
@@ -48,6 +50,9 @@ _ref = {}
 
 
 def problem(pde, N, prec):
+    if pde == "euler2":
+        p = I.Problem(dim=2, N=N, nel=(3, 2), lo=(0.0, 0.0), hi=(10.0, 10.0), prec=prec)
+        return p, I.isentropic_vortex(p)
     if pde == "euler":
         p = I.Problem(dim=3, N=N, nel=(3, 2, 3), lo=(0, 0, 0), hi=(1, 1, 1), prec=prec)
         return p, I.density_wave(p)
