@@ -25,7 +25,8 @@
  *     states (NaN/Inf, density <= 0, pressure <= 0) are detected on the
  *     device by the time-step reduction; asynchronous calls latch the flag and
  *     the next synchronising call returns ADER_ERR_NONFINITE (and clears it).
- *     When the flag is raised the step size of that problem is set to 0.
+ *     While the flag is raised every problem of the context takes a step
+ *     of size 0 (its state and time stay as they are).
  *   - ader_last_error(ctx) returns a message for the last failing call.
  *
  * State layout (caller-owned, FP64, one contiguous device buffer holding all

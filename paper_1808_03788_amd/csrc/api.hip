@@ -168,30 +168,37 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
 
 // dt of every problem from its mesh maximum S: dt = coef / S, clipped so
 // that the last step lands on t_end (when clip is set); resets the maximum.
-__global__ void k_finalize(unsigned long long *smax, int *err, const double *coef, const double *tend,
-                           int clip, const double *t, double *dt, double *tnext, int np) {
-  const int i = threadIdx.x + blockIdx.x * blockDim.x;
-  if (i >= np) return;
-  const double S = __longlong_as_double((long long)smax[i]);
-  smax[i] = 0ull;
-  double d;
-  if (!(S > 0.0) || isinf(S)) {
-    atomicOr(err, 1);
-    d = 0.0;
-  } else {
-    d = coef[i] / S;
+// One workgroup: it first decides whether any S is not a positive finite
+// number, then writes every dt.  While the error flag is raised (by the
+// time-step kernel, by an earlier step, or here) every problem takes dt = 0,
+// independently of thread timing.
+constexpr int kFinBlock = 256;
+__global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax, int *err, const double *coef,
+                                                        const double *tend, int clip, const double *t, double *dt,
+                                                        double *tnext, int np) {
+  const int prior = *err;  // written before this kernel (it writes err only after the barrier)
+  int bad = 0;
+  for (int i = threadIdx.x; i < np; i += kFinBlock) {
+    const double S = __longlong_as_double((long long)smax[i]);
+    if (!(S > 0.0) || isinf(S)) bad = 1;
   }
-  if (*err) d = 0.0;
-  double tn = t[i] + d;
-  if (clip) {
-    const double rem = tend[i] - t[i];
-    if (rem <= d) {  // the last step lands exactly on t_end
-      d = rem > 0.0 ? rem : 0.0;
-      tn = rem > 0.0 ? tend[i] : t[i];
+  const bool stop = __syncthreads_or(bad) || prior;
+  for (int i = threadIdx.x; i < np; i += kFinBlock) {
+    const double S = __longlong_as_double((long long)smax[i]);
+    smax[i] = 0ull;
+    double d = stop ? 0.0 : coef[i] / S;
+    double tn = t[i] + d;
+    if (clip) {
+      const double rem = tend[i] - t[i];
+      if (rem <= d) {  // the last step lands exactly on t_end
+        d = rem > 0.0 ? rem : 0.0;
+        tn = rem > 0.0 ? tend[i] : t[i];
+      }
     }
+    dt[i] = d;
+    tnext[i] = tn;
   }
-  dt[i] = d;
-  tnext[i] = tn;
+  if (bad) atomicOr(err, 1);
 }
 
 __global__ void k_commit(double *t, const double *tnext, int np) {
@@ -477,8 +484,8 @@ ader_status run_cfl(ader_ctx *c, const double *u, int clip) {
     if (st) return st;
   }
   const int np = (int)c->P.size();
-  hipLaunchKernelGGL(k_finalize, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->smax, c->err, c->coef,
-                     c->tend, clip, c->t, c->dt, c->tnext, np);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, c->cur, c->smax, c->err, c->coef, c->tend, clip,
+                     c->t, c->dt, c->tnext, np);
   HIP_OR_FAIL(c, hipGetLastError());
   return ADER_OK;
 }

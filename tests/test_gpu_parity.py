@@ -291,6 +291,29 @@ def test_nonfinite_is_reported(A):
     ctx.close()
 
 
+def test_nonfinite_stops_every_problem(A):
+    """A NaN in one problem of a context raises the flag; while it is raised
+    every problem takes a zero step and keeps its state and time exactly."""
+    import torch
+    probs = [I.density_wave_problem(nel=3, N=2), I.density_wave_problem(nel=2, N=3)]
+    u0 = [I.density_wave(p) for p in probs]
+    u0[0][4, 0, 5] = np.nan
+    ctx = A.Context(probs)
+    try:
+        u = ctx.upload(u0)
+        ctx.step(u, [1e9, 1e9])
+        ctx.step(u, [1e9, 1e9])
+        torch.cuda.synchronize()
+        with pytest.raises(A.AderError) as e:
+            ctx.time()
+        assert e.value.status == A.ADER_ERR_NONFINITE
+        assert list(ctx.last_dt()) == [0.0, 0.0]
+        assert list(ctx.time()) == [0.0, 0.0]
+        assert np.array_equal(ctx.download(u)[1], u0[1])
+    finally:
+        ctx.close()
+
+
 def test_deterministic_and_resume(A):
     import torch
     prob = I.density_wave_problem(nel=4, N=3)
