@@ -292,6 +292,24 @@ class Context:
         self.layouts = [ader_layout(self.ctx, p) for p in range(self.nprob)]
         self.nvars = sum(p.m for p in self.problems)
 
+    def _state(self, u):
+        """The state buffer the kernels will index: a contiguous float64
+        tensor on the GPU with at least state_size values (checked here
+        because the library trusts its pointer arguments)."""
+        t = self.torch
+        if not isinstance(u, t.Tensor) or u.dtype != t.float64 or not u.is_cuda or not u.is_contiguous():
+            raise ValueError("u must be a contiguous float64 GPU tensor")
+        if u.numel() < self.size:
+            raise ValueError(f"u holds {u.numel()} values, the context needs {self.size}")
+        return u
+
+    def _per_problem(self, x, what):
+        """One float64 value per problem (a scalar is broadcast)."""
+        a = np.full(self.nprob, float(x)) if np.isscalar(x) else np.ascontiguousarray(x, dtype=np.float64)
+        if a.shape != (self.nprob,):
+            raise ValueError(f"{what} needs {self.nprob} values, got shape {a.shape}")
+        return a
+
     def close(self):
         if self.ctx:
             ader_destroy(self.ctx)
@@ -307,6 +325,8 @@ class Context:
         return self.torch.empty(self.size, dtype=self.torch.float64, device="cuda")
 
     def upload(self, arrays):
+        if len(arrays) != self.nprob:
+            raise ValueError(f"{len(arrays)} arrays for {self.nprob} problems")
         u = self.empty()
         for (off, cnt), a in zip(self.layouts, arrays):
             a = np.ascontiguousarray(a, dtype=np.float64).reshape(-1)
@@ -315,23 +335,23 @@ class Context:
         return u
 
     def download(self, u):
-        host = u.detach().cpu().numpy()
+        host = self._state(u).detach().cpu().numpy()
         return [host[off:off + cnt].reshape(p.E, p.m, p.nd).copy()
                 for (off, cnt), p in zip(self.layouts, self.problems)]
 
     def cfl_dt(self, u):
-        return ader_cfl_dt(self.ctx, u, self.nprob)
+        return ader_cfl_dt(self.ctx, self._state(u), self.nprob)
 
     def predictor(self, u, dt=None, qhat=False):
         """dt: None (context step) or a sequence of per-problem steps."""
         dt_dev = None
         if dt is not None:
-            dt_dev = self.torch.tensor(np.asarray(dt, dtype=np.float64), device="cuda")
+            dt_dev = self.torch.tensor(self._per_problem(dt, "dt"), device="cuda")
         q = None
         if qhat:
             total = sum(ader_qhat_layout(self.ctx, p)[1] for p in range(self.nprob))
             q = self.torch.zeros(total, dtype=self.torch.float64, device="cuda")
-        ader_predictor(self.ctx, u, dt_dev, q)
+        ader_predictor(self.ctx, self._state(u), dt_dev, q)
         self._dt_keep = dt_dev
         return q
 
@@ -346,20 +366,16 @@ class Context:
     def corrector(self, u, dt=None):
         dt_dev = None
         if dt is not None:
-            dt_dev = self.torch.tensor(np.asarray(dt, dtype=np.float64), device="cuda")
-        ader_corrector(self.ctx, u, dt_dev)
+            dt_dev = self.torch.tensor(self._per_problem(dt, "dt"), device="cuda")
+        ader_corrector(self.ctx, self._state(u), dt_dev)
         self._dt_keep = dt_dev
 
     def step(self, u, t_end):
-        if np.isscalar(t_end):
-            t_end = [t_end] * self.nprob
-        ader_step(self.ctx, u, t_end)
+        ader_step(self.ctx, self._state(u), self._per_problem(t_end, "t_end"))
 
     def run(self, u, t_end, nsteps):
         """nsteps steps replayed as one captured HIP graph."""
-        if np.isscalar(t_end):
-            t_end = [t_end] * self.nprob
-        ader_run(self.ctx, u, t_end, nsteps)
+        ader_run(self.ctx, self._state(u), self._per_problem(t_end, "t_end"), nsteps)
 
     def set_detection(self, enable=True):
         ader_set_detection(self.ctx, enable)
@@ -377,10 +393,10 @@ class Context:
         return ader_time(self.ctx, self.nprob)
 
     def set_time(self, t):
-        ader_set_time(self.ctx, t)
+        ader_set_time(self.ctx, self._per_problem(t, "t"))
 
     def last_dt(self):
         return ader_last_dt(self.ctx, self.nprob)
 
     def totals(self, u):
-        return ader_totals(self.ctx, u, self.nvars)
+        return ader_totals(self.ctx, self._state(u), self.nvars)

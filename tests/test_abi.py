@@ -126,3 +126,24 @@ def test_product_path_does_not_use_oracle():
     csrc = os.path.join(ROOT, "paper_1808_03788_amd", "csrc")
     for f in os.listdir(csrc):
         assert "orc_" not in open(os.path.join(csrc, f)).read(), f
+
+
+def test_binding_rejects_buffers_the_kernels_would_overrun():
+    """The Python Context checks what the library trusts: the state tensor
+    (float64, on the GPU, contiguous, at least state_size values) and one
+    value per problem for t_end, dt and t (checked on the host, no GPU)."""
+    import torch
+    ctx = object.__new__(A.Context)  # the checks only, without a device context
+    ctx.torch, ctx.nprob, ctx.size, ctx.ctx = torch, 2, 10, 0
+    for bad in (torch.zeros(10, dtype=torch.float64),    # host memory
+                torch.zeros(10, dtype=torch.float32),    # wrong type
+                np.zeros(10)):                           # not a tensor
+        with pytest.raises(ValueError):
+            ctx._state(bad)
+    for bad in ([1.0], [1.0, 2.0, 3.0], [[1.0, 2.0]]):
+        with pytest.raises(ValueError):
+            ctx._per_problem(bad, "t_end")
+    assert list(ctx._per_problem(5.0, "t_end")) == [5.0, 5.0]
+    assert list(ctx._per_problem([1, 2], "dt")) == [1.0, 2.0]
+    with pytest.raises(ValueError):
+        ctx.upload([np.zeros(1)])
