@@ -294,10 +294,12 @@ __device__ __forceinline__ float round_bf16(float x) {
 // With kAcc the result is added to the values already in sacc, else it is
 // stored.  With kRoundBF the contraction inputs are rounded to bfloat16.
 // kPart (elasticity only) restricts the line to one row group; variable v
-// of the accumulator is held at (v - kAccShift) * VS.
+// of the accumulator is held at (v - kAccShift) * VS.  With kHold the n x M
+// results go to held[k * M + v] (registers of the caller) instead of sacc.
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0,
-          int kAccShift = 0>
-__device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu) {
+          int kAccShift = 0, bool kHold = false>
+__device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu,
+                                         T *held = nullptr) {
   constexpr int n = N + 1, M = PDE::M;
   constexpr int ST = ipow(n, A);
   static_assert(kPart == 0 || PDE::kElastic, "row groups are an elasticity split");
@@ -352,8 +354,12 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
 #pragma unroll
   for (int k = 0; k < n; k++)
 #pragma unroll
-    for (int v = 0; v < M; v++)
-      if (part_writes<kPart>(v)) sacc[(v - kAccShift) * VS + base + k * ST] = acc[k][v];
+    for (int v = 0; v < M; v++) {
+      if constexpr (kHold)
+        held[k * M + v] = acc[k][v];
+      else if (part_writes<kPart>(v))
+        sacc[(v - kAccShift) * VS + base + k * ST] = acc[k][v];
+    }
 }
 
 // Right-hand side along axis A for all lines of the space-time element
@@ -532,22 +538,56 @@ __device__ __forceinline__ void rhs_axes01(PArg &P, const TQ *sq, T *sacc, T *sa
   }
 }
 
+// Axes 0 and 1 at the same time with one accumulator: the first half of
+// the block stores the lines of axis 0 into sacc while the second half
+// computes those of axis 1 into registers, and adds them after a barrier
+// (used where region R has no room for a second accumulator).
+template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS>
+__device__ __forceinline__ void rhs_axes01_held(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int H = round64(NST / n);
+  static_assert(pair_axes<D, N, BS>(), "two halves of whole wavefronts");
+  const int half = threadIdx.x / H, L = threadIdx.x - half * H;
+  const bool active = L < NST / n;
+  const int l0 = L / NF, r = L - l0 * NF;
+  const int base1 = l0 * ND + r % n + (r / n) * n * n;
+  T held[n * M];
+  if (active) {
+    if (half == 0)
+      line_rhs<D, N, PDE, 0, T, TQ, kRoundBF, NST, false>(P, sq, sacc, l0 * ND + r * n, irho, lam, mu);
+    else if (half == 1)
+      line_rhs<D, N, PDE, 1, T, TQ, kRoundBF, NST, false, 0, 0, true>(P, sq, sacc, base1, irho, lam, mu, held);
+  }
+  __syncthreads();
+  if (active && half == 1)
+#pragma unroll
+    for (int k = 0; k < n; k++)
+#pragma unroll
+      for (int v = 0; v < M; v++) sacc[v * NST + base1 + k * n] += held[k * M + v];
+}
+
 // One Picard sweep: R(q) over all axes, then the time contraction.  With
-// kPair (pair_axes, a second accumulator sacc2 of M NST values) axes 0 and
-// 1 run at the same time and axis 2 then accumulates onto sacc.
+// kPair (pair_axes) axes 0 and 1 run at the same time: kPairTwo with a
+// second accumulator sacc2 of M NST values, kPairHeld with the axis-1
+// results held in registers; axis 2 then accumulates onto sacc.
+constexpr int kPairTwo = 1, kPairHeld = 2;
 template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false,
-          bool kPair = false>
+          int kPair = 0>
 __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu, T *sacc2 = nullptr) {
-  if constexpr (kPair) {
+  if constexpr (kPair != 0) {
     static_assert(!kSplit, "one thread per line");
-    rhs_axes01<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
+    if constexpr (kPair == kPairTwo)
+      rhs_axes01<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
+    else
+      rhs_axes01_held<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 2) {
       rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
-    time_phase<D, N, PDE, T, TO, BS, true>(P, sacc, qout, ureg, dt, sacc2);
+    time_phase<D, N, PDE, T, TO, BS, kPair == kPairTwo>(P, sacc, qout, ureg, dt, sacc2);
     __syncthreads();
     return;
   }
@@ -1258,8 +1298,11 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     } else {
       initial_guess<D, N, PDE, double, false, BS, kSplit>(P, sq, sacc, ureg, dt, irho, lam, mu);
     }
+    // no room for a second FP64 accumulator: paired axes hold axis 1 in registers
+    constexpr int kPair64 = (!kSplit && pair_axes<D, N, BS>()) ? kPairHeld : 0;
     for (int s = 0; s < full; s++)
-      picard_sweep<D, N, PDE, double, double, double, false, BS, kSplit>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
+      picard_sweep<D, N, PDE, double, double, double, false, BS, kSplit, kPair64>(P, sq, sacc, sq, ureg, dt, irho,
+                                                                                 lam, mu);
     predictor_outputs<D, N, PDE, double, BS, kSplit>(P, sq, sacc, ue, ureg, dt, e, qo, irho, lam, mu);
   } else {
     constexpr bool kBF = PREC == kBF16;
@@ -1311,7 +1354,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
       static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");
       float *sacc32b = sacc32 + M * S::NST;
       for (int s = 0; s < full32; s++)
-        picard_sweep<D, N, PDE, float, float, float, kBF, BS, false, true>(P, sq32, sacc32, sq32, ureg, dtf,
+        picard_sweep<D, N, PDE, float, float, float, kBF, BS, false, kPairTwo>(P, sq32, sacc32, sq32, ureg, dtf,
                                                                           (float)irho, (float)lam, (float)mu,
                                                                           sacc32b);
     } else {
@@ -1321,7 +1364,12 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     }
     // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
     // the FP64 accumulator in place
-    picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
+    // paired with axis 1 held in registers where an axis phase spans more
+    // than one wavefront (at N = 3 in 3-D the extra registers cost this
+    // kernel a wavefront of occupancy and the sweep was slower)
+    constexpr int kPairR = (!kSplit && pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairHeld : 0;
+    picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit, kPairR>(P, sq32, sR, sR, ureg, dt, irho, lam,
+                                                                             mu);
     predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
   }
 }
