@@ -152,7 +152,16 @@ ader_status ader_corrector(ader_ctx *ctx, double *u, const double *dt_dev);
 /* One full step of every problem: time step (clipped so that the step ends
  * exactly at t_end_host[p]; a problem already at t_end takes dt = 0),
  * predictor, corrector, time advance.  Host-synchronisation free, so it can
- * be captured into a hipGraph (the captured t_end values are then fixed). */
+ * be captured into a hipGraph (the captured t_end values are then fixed).
+ * The update of a step also takes the wave-speed maxima of the state it
+ * writes (the quantity of ader_cfl_dt), and the next ader_step / ader_run on
+ * the same buffer takes its dt from them instead of reading u again; the
+ * result is the same bit for bit.  Any other call on the context that
+ * touches the state (ader_cfl_dt, ader_predictor, ader_corrector,
+ * ader_set_detection) discards those maxima.  A caller that changes u
+ * outside the library between two steps on the same buffer must call
+ * ader_cfl_dt(ctx, u, NULL) before the next step.  With detection on, every
+ * step reads u with the time-step kernel. */
 ader_status ader_step(ader_ctx *ctx, double *u, const double *t_end_host);
 
 /* nsteps consecutive ader_step calls replayed as one HIP graph.  The graph

@@ -1597,6 +1597,39 @@ __global__ void __launch_bounds__(kBlock) k_face_avg(const FaceArgs *args, const
 
 // ------------------------------------------------------------ update
 
+// Largest |eigenvalue| of the Euler flux Jacobian along each axis at one
+// node, lm[A] = |v_A| + c (Sec. 3, CFL condition), and whether the node is
+// unusable (a value not finite, rho <= 0 or p <= 0).  The time-step kernel
+// and the update (which takes the maxima of the state it writes) both call
+// this function, so that the two give the same bits.
+template <int D>
+__device__ __forceinline__ bool euler_node_speeds(const double *q, double gamma, double *lm) {
+  bool bad = false;
+#pragma unroll
+  for (int v = 0; v < D + 2; v++)
+    if (!isfinite(q[v])) bad = true;
+  const double ir = 1.0 / q[0];
+  double ke = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
+  const double p = (gamma - 1.0) * (q[D + 1] - 0.5 * ke * ir);
+  if (!(q[0] > 0.0) || !(p > 0.0)) bad = true;
+  const double c = sqrt(gamma * p * ir);
+#pragma unroll
+  for (int A = 0; A < D; A++) {
+    const double l = fabs(q[1 + A] * ir) + c;
+    if (!(l >= 0.0)) bad = true;
+    lm[A] = l;
+  }
+  return bad;
+}
+
+// P-wave speed of an element's material (elasticity: the largest
+// |eigenvalue| along every axis).
+__device__ __forceinline__ double elastic_cp(const double *mat, int64_t e) {
+  return sqrt((mat[3 * e + 1] + 2.0 * mat[3 * e + 2]) / mat[3 * e]);
+}
+
 struct UpdArgs {
   const Ops *ops;
   Geom g;
@@ -1606,22 +1639,29 @@ struct UpdArgs {
   const void *GR[3];
   int64_t u_off;       // offset of the problem's u in the state buffer
   int pidx;            // problem index: its time step is dt[pidx]
-  int cx;              // tiles of kUpdChunk*kBlock nodes per x-row
+  int cx;              // tiles of upd_elems() elements per x-row
+  double h[3];         // mesh widths (wave-speed maxima of the new state)
+  const double *mat;   // elasticity: [E][3] material
 };
 
 // u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64
 // arithmetic; face integrals stored as GT).  One thread per node, all M
-// variables; a tile is chunk bx of kUpdChunk*kBlock nodes of the x-row
-// (iy, iz), processed kBlock nodes at a time.
+// variables; a tile is a chunk of upd_elems() whole elements of the x-row
+// (iy, iz), kBlock nodes at a time.  With smax_bits set the tile also takes
+// the wave-speed maxima of the state it writes, the reduction the next
+// step's time step needs (the same per-element quantity as k_cfl), so a
+// step of ader_step does not read u again for it.
 constexpr int kUpdChunk = 4;
+__host__ __device__ constexpr int upd_elems(int D, int N) {
+  return (kUpdChunk * kBlock) / ipow(N + 1, D) > 0 ? (kUpdChunk * kBlock) / ipow(N + 1, D) : 1;
+}
 
 template <int D, int N, class PDE, typename GT>
-__device__ __forceinline__ void update_nodes(const UpdArgs &U, int t, int iy, int iz, double *ubuf,
-                                             double dt) {
+__device__ __forceinline__ void update_node(const UpdArgs &U, int t, int iy, int iz, double *ubuf, double dt,
+                                            double *qn) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
   const int nx = U.g.nel[0], ny = U.g.nel[1], nz = U.g.nel[2];
-  if (t >= nx * ND) return;
   const int ix = t / ND, k = t - ix * ND;
   const int64_t e = ix + (int64_t)nx * (iy + (int64_t)ny * iz);
   const GT *gp[D], *gm[D];
@@ -1651,20 +1691,105 @@ __device__ __forceinline__ void update_nodes(const UpdArgs &U, int t, int iy, in
     for (int A = 0; A < D; A++)
       acc += cp[A] * (double)as_global(gp[A])[v * NF] + cm[A] * (double)as_global(gm[A])[v * NF];
     const double us = ustar[base + v * ND];
-    u[base + v * ND] = dt == 0.0 ? us : us - dt * acc;
+    qn[v] = dt == 0.0 ? us : us - dt * acc;
+    u[base + v * ND] = qn[v];
   }
 }
 
 template <int D, int N, class PDE, typename GT>
 __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const RowTile *tiles, int64_t ntiles,
-                                                   double *u, const double *dt) {
+                                                   double *u, const double *dt, unsigned long long *smax_bits,
+                                                   int *err) {
+  constexpr int M = PDE::M, ND = Shape<D, N>::ND;
+  constexpr int EPT = upd_elems(D, N);
+  constexpr int ROUNDS = (EPT * ND + kBlock - 1) / kBlock;
+  __shared__ double lam[EPT][D];  // per element of the tile: max over its nodes of lambda_A
+  __shared__ int bad_any;
+  const bool speeds = smax_bits != nullptr;
+  const int lane = threadIdx.x & 63;
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const RowTile t = cload(&tiles[tile]);
     const UpdArgs U = cload(&args[t.p]);
     const double d = cload(&dt[t.pidx]);
+    const int iy = (int)(t.yz & 0xffffu), iz = (int)(t.yz >> 16);
+    const int e0 = t.bx * EPT;
+    const int ne = U.g.nel[0] - e0 < EPT ? U.g.nel[0] - e0 : EPT;
+    if (speeds) {
+      for (int i = threadIdx.x; i < EPT * D; i += kBlock) (&lam[0][0])[i] = 0.0;
+      if (threadIdx.x == 0) bad_any = 0;
+      __syncthreads();
+    }
+    bool bad = false;
 #pragma unroll
-    for (int c = 0; c < kUpdChunk; c++)
-      update_nodes<D, N, PDE, GT>(U, (t.bx * kUpdChunk + c) * kBlock + threadIdx.x, (int)(t.yz & 0xffffu), (int)(t.yz >> 16), u, d);
+    for (int r = 0; r < ROUNDS; r++) {
+      const int loc = r * kBlock + threadIdx.x;  // node of the tile
+      const bool act = loc < ne * ND;
+      double qn[M];
+      if (act) update_node<D, N, PDE, GT>(U, e0 * ND + loc, iy, iz, u, d, qn);
+      if constexpr (!PDE::kElastic) {
+        if (speeds) {
+          double lm[D];
+#pragma unroll
+          for (int A = 0; A < D; A++) lm[A] = 0.0;
+          if (act) {
+            bad |= euler_node_speeds<D>(qn, U.g.gamma, lm);
+#pragma unroll
+            for (int A = 0; A < D; A++) lm[A] = fmax(0.0, lm[A]);  // a NaN speed raises the flag instead
+          }
+          // segmented maximum over the lanes of one element (elements are
+          // contiguous runs of lanes), then one LDS atomic per run and axis
+          const int key = act ? loc / ND : -1;
+#pragma unroll
+          for (int off = 1; off < 64; off <<= 1) {
+            const int ko = __shfl_down(key, off, 64);
+#pragma unroll
+            for (int A = 0; A < D; A++) {
+              const double o = __shfl_down(lm[A], off, 64);
+              if (ko == key) lm[A] = fmax(lm[A], o);
+            }
+          }
+          const int kp = __shfl_up(key, 1, 64);
+          if (act && (lane == 0 || kp != key))
+#pragma unroll
+            for (int A = 0; A < D; A++)
+              atomicMax((unsigned long long *)&lam[key][A], (unsigned long long)__double_as_longlong(lm[A]));
+        }
+      } else {
+        if (speeds && act)
+#pragma unroll
+          for (int v = 0; v < M; v++)
+            if (!isfinite(qn[v])) bad = true;
+      }
+    }
+    if (speeds) {
+      if (bad) atomicOr(&bad_any, 1);
+      __syncthreads();
+      if (threadIdx.x < 64) {
+        // S_e = sum_A lm_A / h_A per element, then the tile maximum
+        double smx = 0.0;
+        bool badm = false;
+        for (int el = lane; el < ne; el += 64) {
+          double se = 0.0;
+          if constexpr (PDE::kElastic) {
+            const double cpe = elastic_cp(U.mat, e0 + el + (int64_t)U.g.nel[0] * (iy + (int64_t)U.g.nel[1] * iz));
+            if (!(cpe > 0.0)) badm = true;
+#pragma unroll
+            for (int A = 0; A < D; A++) se += cpe / U.h[A];
+          } else {
+#pragma unroll
+            for (int A = 0; A < D; A++) se += lam[el][A] / U.h[A];
+          }
+          smx = fmax(smx, se);
+        }
+        for (int off = 32; off > 0; off >>= 1) smx = fmax(smx, __shfl_xor(smx, off, 64));
+        if (__any(badm)) bad_any = 1;  // wave 0 only; the other waves wrote bad_any before the barrier
+        if (threadIdx.x == 0) {
+          atomicMax(smax_bits + t.pidx, (unsigned long long)__double_as_longlong(smx));
+          if (bad_any) atomicOr(err, 1);
+        }
+      }
+      __syncthreads();  // lam and bad_any are reused by the next tile
+    }
   }
 }
 
@@ -1713,23 +1838,14 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
         vmax[v] = fmax(vmax[v], q[v]);
       }
       if constexpr (!PDE::kElastic) {
-        const double ir = 1.0 / q[0];
-        double ke = 0.0;
+        double ln[D];
+        if (euler_node_speeds<D>(q, C.g.gamma, ln)) bad = 1;
 #pragma unroll
-        for (int i = 0; i < D; i++) ke += q[1 + i] * q[1 + i];
-        const double p = (C.g.gamma - 1.0) * (q[D + 1] - 0.5 * ke * ir);
-        if (!(q[0] > 0.0) || !(p > 0.0)) bad = 1;
-        const double c = sqrt(C.g.gamma * p * ir);
-#pragma unroll
-        for (int A = 0; A < D; A++) {
-          const double l = fabs(q[1 + A] * ir) + c;
-          if (!(l >= 0.0)) bad = 1;
-          lm[A] = fmax(lm[A], l);
-        }
+        for (int A = 0; A < D; A++) lm[A] = fmax(lm[A], ln[A]);
       }
     }
     if constexpr (PDE::kElastic) {
-      const double cp = sqrt((C.mat[3 * e + 1] + 2.0 * C.mat[3 * e + 2]) / C.mat[3 * e]);
+      const double cp = elastic_cp(C.mat, e);
       if (!(cp > 0.0)) bad = 1;
 #pragma unroll
       for (int A = 0; A < D; A++) lm[A] = cp;

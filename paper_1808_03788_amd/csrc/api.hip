@@ -90,7 +90,9 @@ struct ader_ctx {
   int *flags = nullptr;                                  // device [total elements]
   int64_t total_e = 0;
   std::vector<double> tend_host;                         // values held by tend
-  unsigned long long *smax = nullptr;                      // device [nprob]
+  unsigned long long *smax = nullptr;                      // device [nprob], time-step kernel maxima
+  unsigned long long *smax_f = nullptr;                    // device [nprob], maxima taken by the update
+  const double *fused_u = nullptr;  // state buffer whose maxima smax_f holds (written by the last step)
   int *err = nullptr;                                      // device [1]
   double *partial = nullptr, *sums = nullptr;              // totals scratch
   int64_t total_u = 0, total_q = 0, total_m = 0;
@@ -173,9 +175,11 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
 // time-step kernel, by an earlier step, or here) every problem takes dt = 0,
 // independently of thread timing.
 constexpr int kFinBlock = 256;
-__global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax, int *err, const double *coef,
-                                                        const double *tend, int clip, const double *t, double *dt,
-                                                        double *tnext, int np) {
+// smax is the buffer of maxima this step uses; both it and smax_f (the
+// update's buffer, filled again by this step's update) are cleared.
+__global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax, unsigned long long *smax_f,
+                                                        int *err, const double *coef, const double *tend, int clip,
+                                                        const double *t, double *dt, double *tnext, int np) {
   const int prior = *err;  // written before this kernel (it writes err only after the barrier)
   int bad = 0;
   for (int i = threadIdx.x; i < np; i += kFinBlock) {
@@ -186,6 +190,7 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax
   for (int i = threadIdx.x; i < np; i += kFinBlock) {
     const double S = __longlong_as_double((long long)smax[i]);
     smax[i] = 0ull;
+    smax_f[i] = 0ull;
     double d = stop ? 0.0 : coef[i] / S;
     double tn = t[i] + d;
     if (clip) {
@@ -199,6 +204,11 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax
     tnext[i] = tn;
   }
   if (bad) atomicOr(err, 1);
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  const int i = threadIdx.x + blockIdx.x * blockDim.x;
+  if (i < n) p[i] = 0ull;
 }
 
 __global__ void k_commit(double *t, const double *tnext, int np) {
@@ -431,7 +441,10 @@ ader_status build_class(ader_ctx *c, KClass &k) {
     }
     u.u_off = s.u_off;
     u.pidx = p;
-    u.cx = (int)((blocks_for((int64_t)nx * s.nd) + kUpdChunk - 1) / kUpdChunk);
+    const int ept = upd_elems(s.D, s.N);
+    u.cx = (nx + ept - 1) / ept;
+    for (int ax = 0; ax < 3; ax++) u.h[ax] = s.h[ax];
+    u.mat = s.mat;
     CflArgs &cf = ca[i];
     cf.g = s.g;
     for (int ax = 0; ax < 3; ax++) cf.h[ax] = s.h[ax];
@@ -474,18 +487,26 @@ ader_status build_class(ader_ctx *c, KClass &k) {
   return ADER_OK;
 }
 
-// Per-problem maxima of the wave speed, then every problem's dt (clipped
-// to the t_end values held by c->tend when clip is set).
-ader_status run_cfl(ader_ctx *c, const double *u, int clip) {
+// Per-problem maxima of the wave speed of u into `out` (the time-step kernel).
+ader_status run_maxima(ader_ctx *c, const double *u, unsigned long long *out) {
   for (KClass &k : c->K) {
     Batch b{k.cstart, (int)k.probs.size()};
-    void *args[] = {&k.cargs, &b, &u, &c->smax, &c->err};
+    void *args[] = {&k.cargs, &b, &u, &out, &c->err};
     ader_status st = launch(c, k.cfl, k.ctot, k.cgrid, kBlock, 0, args);
     if (st) return st;
   }
+  return ADER_OK;
+}
+
+// Every problem's dt (clipped to the t_end values held by c->tend when
+// clip is set) from the maxima of u: taken here by the time-step kernel,
+// or (fused) those the previous step's update took of the state it wrote.
+ader_status run_cfl(ader_ctx *c, const double *u, int clip, bool fused = false) {
+  ader_status st;
+  if (!fused && (st = run_maxima(c, u, c->smax))) return st;
   const int np = (int)c->P.size();
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, c->cur, c->smax, c->err, c->coef, c->tend, clip,
-                     c->t, c->dt, c->tnext, np);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinBlock), 0, c->cur, fused ? c->smax_f : c->smax, c->smax_f,
+                     c->err, c->coef, c->tend, clip, c->t, c->dt, c->tnext, np);
   HIP_OR_FAIL(c, hipGetLastError());
   return ADER_OK;
 }
@@ -512,10 +533,13 @@ ader_status run_faces(ader_ctx *c) {
   return ADER_OK;
 }
 
-ader_status run_update(ader_ctx *c, double *u, const double *dt_dev) {
+// The update; with `maxima` it also takes the wave-speed maxima of the new
+// state into smax_f (the next step's time step then needs no pass over u).
+ader_status run_update(ader_ctx *c, double *u, const double *dt_dev, bool maxima = false) {
   const double *dt = dt_dev ? dt_dev : c->dt;
+  unsigned long long *sm = maxima ? c->smax_f : nullptr;
   for (KClass &k : c->K) {
-    void *args[] = {&k.uargs, &k.utiles, &k.utot, &u, &dt};
+    void *args[] = {&k.uargs, &k.utiles, &k.utot, &u, &dt, &sm, &c->err};
     ader_status st = launch(c, k.update, k.utot, k.ugrid, kBlock, 0, args);
     if (st) return st;
   }
@@ -606,13 +630,18 @@ ader_status set_tend(ader_ctx *c, const double *t_end_host) {
 
 // The launches of one step on c->cur: dt, predictor, faces, update, commit
 // of the new time.  Profiling events are recorded only outside captures.
-ader_status step_launches(ader_ctx *c, double *u, bool marks) {
+// With `fused` the step's dt comes from the maxima the previous step's
+// update took (smax_f holds them for this u); else the time-step kernel
+// reads u.  The update takes the maxima of the new state unless detection is
+// on (the time-step kernel then also records the per-element extremes the
+// detection needs).
+ader_status step_launches(ader_ctx *c, double *u, bool marks, bool fused) {
   ader_status st;
   const bool m = marks && c->profile;
-  if ((m && (st = mark(c))) || (st = run_cfl(c, u, 1))) return st;
+  if ((m && (st = mark(c))) || (st = run_cfl(c, u, 1, fused))) return st;
   if ((m && (st = mark(c))) || (st = run_predictor(c, u, nullptr, nullptr))) return st;
   if ((m && (st = mark(c))) || (st = run_faces(c))) return st;
-  if ((m && (st = mark(c))) || (st = run_update(c, u, nullptr))) return st;
+  if ((m && (st = mark(c))) || (st = run_update(c, u, nullptr, !c->detect))) return st;
   if (c->detect && (st = run_detect(c, u))) return st;  // timed with the update stage
   if (m && (st = mark(c))) return st;
   const int np = (int)c->P.size();
@@ -800,6 +829,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   if ((st = dalloc(c, (void **)&c->t, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->tnext, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->smax, nprob * sizeof(unsigned long long)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->smax_f, nprob * sizeof(unsigned long long)))) return bail(st);
   {
     std::vector<double> coef(nprob);
     for (int i = 0; i < nprob; i++) coef[i] = c->P[i].coef;
@@ -815,6 +845,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       hipMemset(c->t, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->tnext, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->smax, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->smax_f, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->err, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     c->msg = "initialisation failed";
     return bail(ADER_ERR_DEVICE);
@@ -928,6 +959,7 @@ ader_status ader_state_size(const ader_ctx *c, int64_t *count) {
 ader_status ader_cfl_dt(ader_ctx *c, const double *u, double *dt_host) {
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  c->fused_u = nullptr;  // the finalisation clears the update's maxima
   ader_status st = run_cfl(c, u, 0);
   if (st || !dt_host) return st;
   HIP_OR_FAIL(c, hipMemcpyAsync(dt_host, c->dt, c->P.size() * sizeof(double), hipMemcpyDeviceToHost,
@@ -938,12 +970,14 @@ ader_status ader_cfl_dt(ader_ctx *c, const double *u, double *dt_host) {
 ader_status ader_predictor(ader_ctx *c, const double *u, const double *dt_dev, double *qhat_out) {
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  c->fused_u = nullptr;
   return run_predictor(c, u, dt_dev, qhat_out);
 }
 
 ader_status ader_corrector(ader_ctx *c, double *u, const double *dt_dev) {
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
+  c->fused_u = nullptr;
   return run_corrector(c, u, dt_dev);
 }
 
@@ -951,7 +985,12 @@ ader_status ader_step(ader_ctx *c, double *u, const double *t_end_host) {
   if (!c) return ADER_ERR_INVALID;
   if (!u || !t_end_host) return fail(c, ADER_ERR_INVALID, "u and t_end must not be NULL");
   ader_status st = set_tend(c, t_end_host);
-  return st ? st : step_launches(c, u, true);
+  if (st) return st;
+  const bool fused = !c->detect && c->fused_u == u;
+  c->fused_u = nullptr;
+  if ((st = step_launches(c, u, true, fused))) return st;
+  c->fused_u = c->detect ? nullptr : u;
+  return ADER_OK;
 }
 
 ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t nsteps) {
@@ -973,7 +1012,10 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
     }
     HIP_OR_FAIL(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
     c->cur = c->gstream;
-    for (int i = 0; i < nsteps && !st; i++) st = step_launches(c, u, false);
+    // every captured step takes its dt from the maxima the update before it
+    // took (the first one from those of the previous replay, or of the pass
+    // below); with detection on, every step runs the time-step kernel
+    for (int i = 0; i < nsteps && !st; i++) st = step_launches(c, u, false, !c->detect);
     c->cur = c->stream;
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(c->gstream, &g);
@@ -991,12 +1033,21 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
     c->g_u = u;
     c->g_steps = nsteps;
   }
+  if (!c->detect && c->fused_u != u) {
+    // the replay's first step needs the maxima of u in smax_f
+    c->fused_u = nullptr;
+    const int np = (int)c->P.size();
+    hipLaunchKernelGGL(k_zero_u64, dim3((np + 255) / 256), dim3(256), 0, c->stream, c->smax_f, np);
+    HIP_OR_FAIL(c, hipGetLastError());
+    if ((st = run_maxima(c, u, c->smax_f))) return st;
+  }
   // order the replay after earlier work on the context stream, and later work after it
   HIP_OR_FAIL(c, hipEventRecord(c->g_in, c->stream));
   HIP_OR_FAIL(c, hipStreamWaitEvent(c->gstream, c->g_in, 0));
   HIP_OR_FAIL(c, hipGraphLaunch(c->gexec, c->gstream));
   HIP_OR_FAIL(c, hipEventRecord(c->g_out, c->gstream));
   HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->g_out, 0));
+  c->fused_u = c->detect ? nullptr : u;
   return ADER_OK;
 }
 
@@ -1020,6 +1071,7 @@ ader_status ader_set_detection(ader_ctx *c, int32_t enable) {
     c->gexec = nullptr;
   }
   c->detect = on;
+  c->fused_u = nullptr;
   for (KClass &k : c->K)
     if ((st = refresh_detection(c, k))) {
       // incomplete records: leave detection off (steps then launch no detection kernel)

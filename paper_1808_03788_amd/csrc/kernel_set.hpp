@@ -94,9 +94,32 @@ KernelSet make_kernel_set() {
   return k;
 }
 
-// Defined in the per-family instantiation units.
-KernelSet kernels_euler2(int N);
-KernelSet kernels_euler3(int N);
-KernelSet kernels_elastic3(int N);
+// Defined in the per-(family, degree) instantiation units (inst_degree.hip).
+#define ADER_DECLARE_FAMILY(fam)                                                                      \
+  KernelSet fam##_N0();                                                                                 \
+  KernelSet fam##_N1();                                                                                 \
+  KernelSet fam##_N2();                                                                                 \
+  KernelSet fam##_N3();                                                                                 \
+  KernelSet fam##_N4();                                                                                 \
+  KernelSet fam##_N5();                                                                                 \
+  KernelSet fam##_N6();                                                                                 \
+  KernelSet fam##_N7();                                                                                 \
+  inline KernelSet fam(int N) {                                                                         \
+    switch (N) {                                                                                        \
+      case 0: return fam##_N0();                                                                        \
+      case 1: return fam##_N1();                                                                        \
+      case 2: return fam##_N2();                                                                        \
+      case 3: return fam##_N3();                                                                        \
+      case 4: return fam##_N4();                                                                        \
+      case 5: return fam##_N5();                                                                        \
+      case 6: return fam##_N6();                                                                        \
+      case 7: return fam##_N7();                                                                        \
+      default: return KernelSet{};                                                                      \
+    }                                                                                                   \
+  }
+ADER_DECLARE_FAMILY(kernels_euler2)
+ADER_DECLARE_FAMILY(kernels_euler3)
+ADER_DECLARE_FAMILY(kernels_elastic3)
+#undef ADER_DECLARE_FAMILY
 
 }  // namespace ader

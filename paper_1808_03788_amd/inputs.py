@@ -288,6 +288,15 @@ def linf(a: np.ndarray, ref: np.ndarray) -> float:
     return float(np.max(np.abs(a - ref)))
 
 
+def rel_linf(a: np.ndarray, ref: np.ndarray) -> float:
+    """Max over variables of max |a - ref| / max |ref| over the nodes of all
+    elements (absolute where the reference variable is identically zero);
+    a and ref are [E][m][nd]."""
+    d = np.abs(np.asarray(a) - np.asarray(ref)).max(axis=(0, 2))
+    s = np.abs(np.asarray(ref)).max(axis=(0, 2))
+    return float(np.where(s > 0, d / np.where(s > 0, s, 1.0), d).max())
+
+
 def homogeneous_material(prob: Problem, rho=2500.0, cp=4500.0) -> np.ndarray:
     cs = cp / math.sqrt(3.0)
     mu = rho * cs * cs

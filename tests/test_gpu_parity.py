@@ -51,10 +51,18 @@ def orc_run(orc, prob, u0, steps, t_end=1e9):
     return u, t
 
 
+# Per-variable max-norm bound, as a multiple of the relative L2 bound.
+LINF_FACTOR = 10.0
+
+
 def check(prob, a, ref, tol=TOL64, what=""):
+    """Per variable: relative discrete L2 error <= tol and relative max-norm
+    error <= LINF_FACTOR * tol (each the max over variables)."""
     err = I.rel_l2(prob, a, ref)
-    say(f"  {what} rel_l2={err:.3e} linf={I.linf(a, ref):.3e}")
+    ei = I.rel_linf(a, ref)
+    say(f"  {what} rel_l2={err:.3e} rel_linf={ei:.3e}")
     assert err <= tol, (what, err)
+    assert ei <= LINF_FACTOR * tol, (what, "linf", ei)
 
 
 CASES = [

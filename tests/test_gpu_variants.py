@@ -95,6 +95,9 @@ def test_forced_variant_vs_oracle(A, orc, pde, N, prec, variant):
         ug = ctx.download(u)[0]
     finally:
         ctx.close()
-    err = I.rel_l2(prob, ug, oracle_ref(orc, pde, N))
-    say(f"  rel_l2={err:.3e}")
+    ref = oracle_ref(orc, pde, N)
+    err = I.rel_l2(prob, ug, ref)
+    ei = I.rel_linf(ug, ref)
+    say(f"  rel_l2={err:.3e} rel_linf={ei:.3e}")
     assert err <= TOL[prec], (variant, N, err)
+    assert ei <= 10 * TOL[prec], (variant, N, "linf", ei)
