@@ -206,6 +206,24 @@ ader_status ader_last_dt(ader_ctx *ctx, double *dt_host);
  * deterministic order), into host [sum over problems of m]; synchronises. */
 ader_status ader_totals(ader_ctx *ctx, const double *u, double *sums_host);
 
+/* ader_totals without a context and without any allocation, for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  The same domain
+ * integrals as ader_totals, bit for bit (same kernels and grid), of ONE
+ * problem whose state u (device, [E][m][(N+1)^d], the layout of ader_layout
+ * for a single-problem context) is described by *prob (validated as in
+ * ader_create), written to sums_dev (device, m doubles, caller-owned)
+ * asynchronously on the HIP stream hip_stream (NULL = default stream); the
+ * call does not synchronise.  The per-block partial sums live in a static
+ * device array of the library of 512 x 9 doubles (36 KB), held by every GPU
+ * the library runs on until the process ends; every problem size fits it
+ * (at most 9 variables; more would be ADER_ERR_UNSUPPORTED).  All calls on
+ * one GPU share that array: calls that overlap on one GPU (on different
+ * streams or threads) race and must be ordered by the caller.  Errors:
+ * ADER_ERR_INVALID (NULL pointers, a bad problem), ADER_ERR_DEVICE (a HIP
+ * call failed); the message is ader_last_error(NULL). */
+ader_status ader_totals_noalloc(const ader_problem *prob, const double *u, double *sums_dev, void *hip_stream);
+
 /* Per-stage device timing of ader_step.  With enable != 0 the context
  * records HIP events on its own stream at the boundaries of the four stages
  * of every following ader_step: 0 time-step reduction, 1 predictor, 2 face

@@ -28,6 +28,7 @@ EXPORTS = [
     "ader_set_time", "ader_last_dt", "ader_totals", "ader_last_error",
     "ader_stability_alpha", "ader_basis", "ader_version", "ader_profile", "ader_stage_times",
     "ader_describe", "ader_run", "ader_set_detection", "ader_detect_flags",
+    "ader_totals_noalloc",
 ]
 
 
@@ -76,6 +77,7 @@ def lib():
         L.ader_set_time.argtypes = [_VP, _DP]
         L.ader_last_dt.argtypes = [_VP, _DP]
         L.ader_totals.argtypes = [_VP, _VP, _DP]
+        L.ader_totals_noalloc.argtypes = [C.POINTER(ader_problem), _VP, _VP, _VP]
         L.ader_last_error.argtypes = [_VP]
         L.ader_last_error.restype = C.c_char_p
         L.ader_stability_alpha.argtypes = [C.c_int32, _DP]
@@ -243,6 +245,15 @@ def ader_totals(ctx: int, u, nvars: int) -> np.ndarray:
     out = np.zeros(nvars)
     _check(lib().ader_totals(_VP(ctx), _VP(_ptr(u)), out.ctypes.data_as(_DP)), ctx)
     return out
+
+
+def ader_totals_noalloc(prob, u, sums_dev, stream: int = 0):
+    """Domain integrals of one problem's state u into the device buffer
+    sums_dev (m doubles), without a context and without allocation; does not
+    synchronise."""
+    keep: list = []
+    desc = make_problem(prob, keep)
+    _check(lib().ader_totals_noalloc(C.byref(desc), _VP(_ptr(u)), _VP(_ptr(sums_dev)), _VP(stream)))
 
 
 def ader_profile(ctx: int, enable: bool):

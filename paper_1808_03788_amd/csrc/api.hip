@@ -257,6 +257,35 @@ __global__ void k_totals_final(const double *partial, int nblk, int m, double *o
 
 int64_t blocks_for(int64_t work) { return (work + kBlock - 1) / kBlock; }
 
+// Scratch of ader_totals_noalloc: the per-block partial sums of
+// k_totals_partial, kTotBlocks x (at most 9 variables) doubles (36 KB).  Each
+// device holds its own copy until the process ends.  In host code the name
+// only stands for the array; kernels get its device address, taken once per
+// device with hipGetSymbolAddress.
+constexpr int kScratchVars = 9;
+__device__ __align__(256) double scratch[kTotBlocks * kScratchVars];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// The device address of `scratch` on the current device (looked up on the
+// first call per device).
+hipError_t scratch_address(double **out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = (double *)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
 // One batched launch: `grid` persistent workgroups over `tiles` tiles.
 ader_status launch(ader_ctx *c, const void *fn, int64_t tiles, int grid, int threads, size_t shmem,
                    void **args) {
@@ -1131,6 +1160,55 @@ ader_status ader_totals(ader_ctx *c, const double *u, double *sums_host) {
   HIP_OR_FAIL(c, hipMemcpyAsync(sums_host, c->sums, (size_t)c->total_m * sizeof(double),
                                 hipMemcpyDeviceToHost, c->stream));
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream));
+  return ADER_OK;
+}
+
+ader_status ader_totals_noalloc(const ader_problem *prob, const double *u, double *sums_dev, void *hip_stream) {
+  if (!prob || !u || !sums_dev) {
+    g_create_msg = "prob, u and sums_dev must not be NULL";
+    return ADER_ERR_INVALID;
+  }
+  ader_ctx tmp;  // only carries the message of validate()
+  ader_status st = validate(&tmp, *prob, 0);
+  if (st) {
+    g_create_msg = tmp.msg;
+    return st;
+  }
+  const int D = prob->dim, N = prob->degree, n = N + 1;
+  const int m = prob->pde == ADER_EULER ? D + 2 : 9;
+  if (m > kScratchVars) {  // the scratch holds kTotBlocks partial sums of at most kScratchVars variables
+    g_create_msg = "more variables than the static scratch holds";
+    return ADER_ERR_UNSUPPORTED;
+  }
+  int nd = 1;
+  int64_t E = 1;
+  double vol = 1.0;
+  for (int a = 0; a < D; a++) {
+    nd *= n;
+    E *= prob->nelem[a];
+    vol *= (prob->hi[a] - prob->lo[a]) / prob->nelem[a];
+  }
+  Ops ops;
+  if (build_ops(N, &ops)) {
+    g_create_msg = "basis construction failed";
+    return ADER_ERR_INVALID;
+  }
+  double *part = nullptr;
+  hipError_t e = scratch_address(&part);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_msg = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return ADER_ERR_DEVICE;
+  }
+  hipStream_t s = (hipStream_t)hip_stream;
+  // the same kernels and grid as ader_totals: the same sums bit for bit
+  hipLaunchKernelGGL(k_totals_partial, dim3(kTotBlocks), dim3(kBlock), 0, s, u, E, m, nd, n, D, ops, vol, part);
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(64), 0, s, part, kTotBlocks, m, sums_dev);
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    g_create_msg = std::string("totals launch: ") + hipGetErrorString(e);
+    return ADER_ERR_DEVICE;
+  }
   return ADER_OK;
 }
 
