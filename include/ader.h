@@ -59,11 +59,14 @@ typedef enum {
 typedef enum { ADER_EULER = 0, ADER_ELASTIC = 1 } ader_pde;
 
 /* Arithmetic of the predictor's Picard sweeps.  ADER_FP64: every sweep in
- * FP64.  ADER_FP32: sweeps 1..P-1 in FP32 (operator contractions on MFMA
- * with FP32 accumulation), the last sweep in FP64.  ADER_BF16: like FP32 but
- * the contraction inputs are rounded to bfloat16.  The corrector's update
- * u^{n+1} = u^n + dt*R, the time-step reduction and the conservation sums are
- * FP64 in every mode. */
+ * FP64.  ADER_FP32: sweeps 1..P-1 in FP32 with FP32 accumulation, the last
+ * sweep in FP64; the FP32 operator contractions run either on the matrix
+ * cores (v_mfma_f32_4x4x1, rows in groups of four, the rest on VALU) or as
+ * VALU FMAs, whichever the timing at ader_create finds faster for the
+ * configuration (ader_describe names the variant in use: fp32-mfma-* or
+ * fp32-valu-*).  ADER_BF16: like FP32 but the contraction inputs are
+ * rounded to bfloat16.  The corrector's update u^{n+1} = u^n + dt*R, the
+ * time-step reduction and the conservation sums are FP64 in every mode. */
 typedef enum { ADER_FP64 = 0, ADER_FP32 = 1, ADER_BF16 = 2 } ader_prec;
 
 typedef struct {

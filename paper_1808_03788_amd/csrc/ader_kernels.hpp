@@ -171,7 +171,7 @@ struct OpsSweep {
   float DAf[3][kMaxN * kMaxN];
   float Tf[kMaxN * kMaxN];
   float Trowf[kMaxN];
-  float Df[kMaxN * kMaxN];   // unscaled Dhat (MFMA operands, scaled after the contraction)
+  float Dhf[kMaxN * kMaxN];  // unscaled Dhat (MFMA sweeps)
   double VA[3][kMaxN * kMaxN];  // (1/h_A) V: volume operator of axis A
   double xi[kMaxN];             // time nodes (initial guesses)
   float xif[kMaxN];
@@ -775,10 +775,21 @@ __device__ __forceinline__ void initial_guess(PArg &P, T *sq, T *sk, const doubl
 // Every lane owns one line (n nodes of one axis, all M variables) and feeds
 // its own value at node j as B; the A operand of lane 4b+i is the operator
 // entry Op[4c+i][j].  One instruction per node j (K = 1, no padding) and per
-// group c of four output nodes thus leaves out[k = 4c+i] = sum_j Op[k][j] X[j]
+// group c of four output rows thus leaves out[k = 4c+i] = sum_j Op[k][j] X[j]
 // of the lane's own line in register i: no data moves between lanes.
+//
+// Output rows go in groups of four to the matrix cores while a group is at
+// least 3/4 full; the rest (one row at n = 5, two at n = 6) is computed on
+// VALU FMAs with the operator row as a scalar operand, concurrently with
+// the matrix cores.  The MFMA accumulators start from the value to add (the
+// earlier axes' sum, or u in the time contraction), so no extra add is
+// needed.
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+
+// Row groups of four on MFMA, and rows left to VALU, for n nodes.
+__host__ __device__ constexpr int mfma_groups(int n) { return (n == 5 || n == 6) ? 1 : (n + 3) / 4; }
+__host__ __device__ constexpr int mfma_valu_rows(int n) { return n - 4 * mfma_groups(n) > 0 ? n - 4 * mfma_groups(n) : 0; }
 
 template <int D, int N>
 __device__ __forceinline__ int line_base(int line, int ST) {
@@ -787,81 +798,142 @@ __device__ __forceinline__ int line_base(int line, int ST) {
   return l0 * S::ND + (r % ST) + (r / ST) * ST * S::n;
 }
 
-template <int D, int N, class PDE, int A, int BS>
-__device__ __forceinline__ void rhs_axis_mfma(PArg &P, const float *sq, float *sacc,
-                                              const float (&Da)[2][N + 1], float irho, float lam,
-                                              float mu) {
+// MFMA operands of a lane, loaded once per element: rows 4c + (lane & 3) of
+// the unscaled Dhat (zero past row n-1) and of (-dt/h_0) T (Euler) or dt T
+// (elasticity).  The Euler sweeps
+// accumulate S = sum_A (h_0/h_A) Dhat_A F_A (Euler; the factor is applied
+// to the flux only when h_A != h_0) and the time contraction multiplies by
+// -dt/h_0, so one operand set serves every axis.  Elasticity applies -1/h_A
+// through the coefficients of B_A.
+template <int N>
+struct MfmaOps {
+  static constexpr int n = N + 1, G = mfma_groups(N + 1);
+  float D[G][n];
+  float T[G][n];
+};
+
+template <int N, class PDE>
+__device__ __forceinline__ void load_mfma_ops(PArg &P, float dt, MfmaOps<N> &o) {
+  constexpr int n = N + 1, G = mfma_groups(n);
+  const int lane = threadIdx.x & 63;
+  const float sT = PDE::kElastic ? dt : -dt * (float)P.g.inv_h[0];
+#pragma unroll
+  for (int c = 0; c < G; c++)
+#pragma unroll
+    for (int j = 0; j < n; j++) {
+      const int k = 4 * c + (lane & 3);
+      o.D[c][j] = k < n ? P.sw->Dhf[k * kMaxN + j] : 0.f;
+      o.T[c][j] = k < n ? sT * P.sw->Tf[k * kMaxN + j] : 0.f;
+    }
+}
+
+// Right-hand side along axis A for the lines L0 + lane of one wavefront
+// (all lanes take part in the MFMAs; lanes past the last line compute on
+// the line L0 and store nothing), written to sacc (kAcc: added to it), in
+// the scaling of MfmaOps.
+template <int D, int N, class PDE, int A, bool kAcc>
+__device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const float *sq, float *sacc, int L0,
+                                           float irho, float lam, float mu) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, NST = S::NST;
   constexpr int ST = ipow(n, A);
   constexpr int NL = NST / n;
-  constexpr int NC = (n + 3) / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float ih = (float)P.g.inv_h[A];
-  for (int L0 = wave * 64; L0 < NL; L0 += BS) {
-    const bool own = L0 + lane < NL;
-    const int base = line_base<D, N>(own ? L0 + lane : L0, ST);
-    float X[n][M];
+  constexpr int G = mfma_groups(n), VR = mfma_valu_rows(n);
+  const int lane = threadIdx.x & 63;
+  const bool own = L0 + lane < NL;
+  const int base = line_base<D, N>(own ? L0 + lane : L0, ST);
+  float X[n][M];
+  // Euler: flux scale h_0/h_A (1 on cubic elements: no multiply)
+  const float fs = (float)(P.g.inv_h[A] / P.g.inv_h[0]);
+  const bool scale = !PDE::kElastic && A > 0 && P.g.inv_h[A] != P.g.inv_h[0];
 #pragma unroll
-    for (int j = 0; j < n; j++) {
-      float q[M];
+  for (int j = 0; j < n; j++) {
+    float q[M];
 #pragma unroll
-      for (int v = 0; v < M; v++) q[v] = sq[v * NST + base + j * ST];
-      if constexpr (!PDE::kElastic) euler_flux<D, A, float>(q, (float)(P.g.gamma - 1.0), X[j]);
-      else
+    for (int v = 0; v < M; v++) q[v] = sq[v * NST + base + j * ST];
+    if constexpr (!PDE::kElastic) {
+      euler_flux<D, A, float>(q, (float)(P.g.gamma - 1.0), X[j]);
+      if (scale)
 #pragma unroll
-        for (int v = 0; v < M; v++) X[j][v] = q[v];
+        for (int v = 0; v < M; v++) X[j][v] *= fs;
+    } else {
+#pragma unroll
+      for (int v = 0; v < M; v++) X[j][v] = q[v];
     }
-    f4v acc[NC][M];
+  }
+  f4v acc[G][M];
+  float accv[VR > 0 ? VR : 1][M];
 #pragma unroll
-    for (int c = 0; c < NC; c++)
+  for (int v = 0; v < M; v++) {
 #pragma unroll
-      for (int v = 0; v < M; v++) acc[c][v] = f4v{0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < G; c++) {
+      // Euler: start from the earlier axes' sum (elasticity adds after B_A)
 #pragma unroll
-    for (int j = 0; j < n; j++)
-#pragma unroll
-      for (int c = 0; c < NC; c++)
-#pragma unroll
-        for (int v = 0; v < M; v++)
-          acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(Da[c][j], X[j][v], acc[c][v], 0, 0, 0);
-    if (own) {
-#pragma unroll
-      for (int k = 0; k < n; k++) {
-        float out[M];
-        if constexpr (!PDE::kElastic) {
-#pragma unroll
-          for (int v = 0; v < M; v++) out[v] = -acc[k / 4][v][k % 4] * ih;
-        } else {
-          float g[M], bg[M];
-#pragma unroll
-          for (int v = 0; v < M; v++) g[v] = acc[k / 4][v][k % 4];
-          elastic_bg<A, float>(g, irho, lam, mu, bg);
-#pragma unroll
-          for (int v = 0; v < M; v++) out[v] = -bg[v] * ih;
-        }
-#pragma unroll
-        for (int v = 0; v < M; v++) {
-          const int idx = v * NST + base + k * ST;
-          if (A == 0) sacc[idx] = out[v];
-          else sacc[idx] += out[v];
-        }
+      for (int i = 0; i < 4; i++) {
+        const int k = 4 * c + i;
+        acc[c][v][i] = (!PDE::kElastic && kAcc && own && k < n) ? sacc[v * NST + base + k * ST] : 0.f;
       }
+    }
+#pragma unroll
+    for (int r = 0; r < VR; r++)
+      accv[r][v] = (!PDE::kElastic && kAcc && own) ? sacc[v * NST + base + (4 * G + r) * ST] : 0.f;
+  }
+#pragma unroll
+  for (int j = 0; j < n; j++)
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+#pragma unroll
+      for (int c = 0; c < G; c++) acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.D[c][j], X[j][v], acc[c][v], 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < VR; r++) accv[r][v] += cload(&P.sw->Dhf[(4 * G + r) * kMaxN + j]) * X[j][v];
+    }
+  if (!own) return;
+  // elasticity: B_A with -1/h_A folded into its coefficients
+  const float sh = PDE::kElastic ? -(float)P.g.inv_h[A] : 1.f;
+  const float irh = irho * sh, lah = lam * sh, muh = mu * sh;
+#pragma unroll
+  for (int k = 0; k < n; k++) {
+    float g[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) g[v] = k < 4 * G ? acc[k / 4][v][k % 4] : accv[k >= 4 * G ? k - 4 * G : 0][v];
+    if constexpr (PDE::kElastic) {
+      float bg[M];
+      elastic_bg<A, float>(g, irh, lah, muh, bg);
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+        const int idx = v * NST + base + k * ST;
+        sacc[idx] = kAcc ? sacc[idx] + bg[v] : bg[v];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < M; v++) sacc[v * NST + base + k * ST] = g[v];
     }
   }
 }
 
-// Time contraction on MFMA: lane owns the time line (v,k).  One extra
-// instruction with A = 1 and B = u seeds every output with u, so the result
-// is q(l) = u + sum_j T[l][j] (dt R(j)).
-template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void time_phase_mfma(const float *sacc, float *sq, const double *ureg, float dt,
-                                                const float (&Ta)[2][N + 1]) {
+template <int D, int N, class PDE, int A, bool kAcc, int WAVES, int W0 = 0>
+__device__ __forceinline__ void mfma_axis(PArg &P, const MfmaOps<N> &o, const float *sq, float *sacc, float irho,
+                                          float lam, float mu) {
+  constexpr int NL = Shape<D, N>::NST / (N + 1);
+  const int wave = (threadIdx.x >> 6) - W0;
+  for (int L0 = wave * 64; L0 < NL; L0 += WAVES * 64)
+    mfma_lines<D, N, PDE, A, kAcc>(P, o, sq, sacc, L0, irho, lam, mu);
+}
+
+// Time contraction on MFMA: the lane owns the time line (v, k), thread
+// i = threadIdx.x + r BS as in time_phase; q(l) = u + sum_j (c T)[l][j] S(j)
+// with S the sum of the accumulators (two with kTwo) and c = -dt/h_0 for
+// Euler (the accumulators hold the unscaled sum) or dt for elasticity.
+template <int D, int N, class PDE, int BS, bool kTwo>
+__device__ __forceinline__ void mfma_time(PArg &P, const MfmaOps<N> &o, const float *sacc, const float *sacc2,
+                                          float *sq, const double *ureg, float dt) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NTL = M * ND;
-  constexpr int NC = (n + 3) / 4;
+  constexpr int G = mfma_groups(n), VR = mfma_valu_rows(n);
   constexpr int NU = TimeItems<D, N, M, BS>::value;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const float cT = PDE::kElastic ? dt : -dt * (float)P.g.inv_h[0];
 #pragma unroll
   for (int r = 0; r < NU; r++) {
     const int T0 = wave * 64 + r * BS;
@@ -871,37 +943,58 @@ __device__ __forceinline__ void time_phase_mfma(const float *sacc, float *sq, co
     const int v = Lt / ND, k = Lt - v * ND;
     float b[n];
 #pragma unroll
-    for (int j = 0; j < n; j++) b[j] = dt * sacc[v * NST + j * ND + k];
+    for (int j = 0; j < n; j++) {
+      b[j] = sacc[v * NST + j * ND + k];
+      if constexpr (kTwo) b[j] += sacc2[v * NST + j * ND + k];
+    }
     const float u0 = (float)ureg[r];
-    f4v acc[NC];
+    f4v acc[G];
+    float accv[VR > 0 ? VR : 1];
 #pragma unroll
-    for (int c = 0; c < NC; c++)
-      acc[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(1.0f, u0, f4v{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    for (int c = 0; c < G; c++) acc[c] = f4v{u0, u0, u0, u0};
 #pragma unroll
-    for (int j = 0; j < n; j++)
+    for (int q = 0; q < VR; q++) accv[q] = u0;
 #pragma unroll
-      for (int c = 0; c < NC; c++) acc[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(Ta[c][j], b[j], acc[c], 0, 0, 0);
+    for (int j = 0; j < n; j++) {
+#pragma unroll
+      for (int c = 0; c < G; c++) acc[c] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.T[c][j], b[j], acc[c], 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < VR; q++) accv[q] += (cT * opT<float>(P, (4 * G + q) * kMaxN + j)) * b[j];
+    }
     if (own)
 #pragma unroll
-      for (int l = 0; l < n; l++) sq[v * NST + l * ND + k] = acc[l / 4][l % 4];
+      for (int l = 0; l < n; l++) sq[v * NST + l * ND + k] = l < 4 * G ? acc[l / 4][l % 4] : accv[l >= 4 * G ? l - 4 * G : 0];
   }
 }
 
+// One FP32 Picard sweep with MFMA contractions.  With pair_axes the lines
+// of axes 0 and 1 run at the same time on the two halves of the block into
+// two accumulators (as rhs_axes01); axis 2 then accumulates onto the first.
 template <int D, int N, class PDE, int BS>
-__device__ __forceinline__ void picard_sweep_mfma(PArg &P, float *sq, float *sacc, const double *ureg,
-                                                  float dt, float irho, float lam, float mu,
-                                                  const float (&Da)[2][N + 1], const float (&Ta)[2][N + 1]) {
-  rhs_axis_mfma<D, N, PDE, 0, BS>(P, sq, sacc, Da, irho, lam, mu);
-  __syncthreads();
-  if constexpr (D > 1) {
-    rhs_axis_mfma<D, N, PDE, 1, BS>(P, sq, sacc, Da, irho, lam, mu);
+__device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, float *sq, float *sacc, float *sacc2,
+                                                  const double *ureg, float dt, float irho, float lam, float mu) {
+  constexpr int NW = BS / 64;
+  constexpr bool kPair = pair_axes<D, N, BS>();
+  if constexpr (kPair) {
+    constexpr int HW = round64(ipow(N + 1, D)) / 64;  // wavefronts per half
+    if ((int)(threadIdx.x >> 6) < HW)
+      mfma_axis<D, N, PDE, 0, false, HW, 0>(P, o, sq, sacc, irho, lam, mu);
+    else if ((int)(threadIdx.x >> 6) < 2 * HW)
+      mfma_axis<D, N, PDE, 1, false, HW, HW>(P, o, sq, sacc2, irho, lam, mu);
     __syncthreads();
+  } else {
+    mfma_axis<D, N, PDE, 0, false, NW>(P, o, sq, sacc, irho, lam, mu);
+    __syncthreads();
+    if constexpr (D > 1) {
+      mfma_axis<D, N, PDE, 1, true, NW>(P, o, sq, sacc, irho, lam, mu);
+      __syncthreads();
+    }
   }
   if constexpr (D > 2) {
-    rhs_axis_mfma<D, N, PDE, 2, BS>(P, sq, sacc, Da, irho, lam, mu);
+    mfma_axis<D, N, PDE, 2, true, NW>(P, o, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
-  time_phase_mfma<D, N, PDE, BS>(sacc, sq, ureg, dt, Ta);
+  mfma_time<D, N, PDE, BS, kPair>(P, o, sacc, sacc2, sq, ureg, dt);
   __syncthreads();
 }
 
@@ -1336,19 +1429,12 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
                                                      (float)mu);
     }
     if constexpr (PREC == kFP32 && kMfma) {
-      // per-lane A operands: operator rows k = 4c + (lane & 3)
-      float Db[2][n], Tb[2][n];
-      const int lq = threadIdx.x & 3;
-#pragma unroll
-      for (int c = 0; c < 2; c++)
-#pragma unroll
-        for (int j = 0; j < n; j++) {
-          const int k = 4 * c + lq;
-          Db[c][j] = k < n ? cload(&P.sw->Df[k * kMaxN + j]) : 0.f;
-          Tb[c][j] = k < n ? cload(&P.sw->Tf[k * kMaxN + j]) : 0.f;
-        }
+      float *sacc32b = pair_axes<D, N, BS>() ? sacc32 + M * S::NST : nullptr;
+      static_assert(!pair_axes<D, N, BS>() || 2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators");
+      MfmaOps<N> mo;
+      load_mfma_ops<N, PDE>(P, dtf, mo);
       for (int s = 0; s < full32; s++)
-        picard_sweep_mfma<D, N, PDE, BS>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam, (float)mu, Db, Tb);
+        picard_sweep_mfma<D, N, PDE, BS>(P, mo, sq32, sacc32, sacc32b, ureg, dtf, (float)irho, (float)lam, (float)mu);
     } else if constexpr (!kSplit && pair_axes<D, N, BS>()) {
       // the FP32 accumulator fills half of region R: the second one takes the other half
       static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");
@@ -1380,8 +1466,24 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
 // index of the element phases live across iterations and cost occupancy, so
 // each workgroup takes a single element.  u, dt and the optional q-hat output
 // are the call's buffers (per-problem offsets in the record).
+// Waves per SIMD the register allocation must allow: as many as the LDS of
+// the FP32 MFMA variants lets reside (their matrix accumulators would
+// otherwise push the allocation past it); 1 (no constraint) for the others.
+template <int D, int N, int M, int PREC, bool kMfma, int kBFac>
+__host__ __device__ constexpr int pred_waves_per_eu() {
+  if constexpr (!kMfma) {
+    return 1;
+  } else {
+    constexpr size_t lds = PredLds<D, N, M, PREC>::A + PredLds<D, N, M, PREC>::R;
+    constexpr int blocks = (int)((160u * 1024u) / lds);
+    constexpr int w = blocks * pred_block(D, N, kBFac) / 64 / 4;
+    return w < 1 ? 1 : (w > 8 ? 8 : w);
+  }
+}
+
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
 __global__ void __launch_bounds__(pred_block(D, N, kBFac))
+    __attribute__((amdgpu_waves_per_eu(pred_waves_per_eu<D, N, PDE::M, PREC, kMfma, kBFac>())))
     k_predictor(const PredArgs *args, const Batch b, const double *u, const double *dt, double *qhat) {
   constexpr int M = PDE::M, ND = Shape<D, N>::ND, NST = Shape<D, N>::NST;
   extern __shared__ __align__(16) unsigned char smem_raw[];

@@ -402,6 +402,8 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
   void *args[] = {&a_dev, &b, &ut, &dtp, &qn};
   double best = 1e30;
   PredVariant bestv = k.pv;
+  const char *tl = getenv("ADER_TUNE_LOG");  // print every candidate's time
+  const bool tune_log = tl && *tl && strcmp(tl, "0") != 0;
   st = ADER_OK;
   for (const PredVariant &v : cand) {
     const int grid = (int)Et;  // one element per workgroup
@@ -413,6 +415,7 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
     float ms = 0.f;
     HIP_OR_FAIL(c, hipEventElapsedTime(&ms, e0, e1));
     if (st) break;
+    if (tune_log) fprintf(stderr, "[ader tune] %s %s %.4f ms\n", key.c_str(), v.name, ms / 3.0);
     if (ms / 3.0 < best) {
       best = ms / 3.0;
       bestv = v;
@@ -781,7 +784,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       }
       s.sw.T[k] = s.ops.T[k];
       s.sw.Tf[k] = (float)s.ops.T[k];
-      s.sw.Df[k] = (float)s.ops.D[k];
+      s.sw.Dhf[k] = (float)s.ops.D[k];
       for (int a = 0; a < 3; a++) s.sw.VA[a][k] = s.g.inv_h[a] * s.ops.V[k];
     }
     for (int k = 0; k < kMaxN; k++) {
