@@ -27,6 +27,20 @@ int build_ops(int N, Ops *out);
 // Host: CFL coefficient alpha_N (1-D von Neumann limit of the scheme).
 double stability_alpha(int N);
 
+// Lines of one axis phase of the predictor are assigned to slots (slot s:
+// wavefront s / 64, lane s % 64); at most kMaxSlots slots per axis (n^D
+// lines rounded up to whole wavefronts, n^D <= 512).  An entry is the LDS
+// offset of the line's first node in the space-time element, or
+// kEmptySlot.
+constexpr int kMaxSlots = 512;
+constexpr uint16_t kEmptySlot = 0xffff;
+// Host: the slot table of axis A for dimension D and degree N: within every
+// wavefront, the line whose base is congruent to r modulo 64 goes to lane
+// r where possible, so that the 4-byte (and 8-byte) LDS accesses of a
+// phase fall in distinct banks; lines that cannot be placed so take the
+// remaining free slots.
+void line_slots(int D, int N, int A, uint16_t *out);
+
 // Per-problem geometry/physics handed to the kernels by value.
 struct Geom {
   int nel[3];

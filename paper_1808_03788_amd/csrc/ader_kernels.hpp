@@ -172,6 +172,7 @@ struct OpsSweep {
   float Tf[kMaxN * kMaxN];
   float Trowf[kMaxN];
   float Dhf[kMaxN * kMaxN];  // unscaled Dhat (MFMA sweeps)
+  uint16_t ls[3][kMaxSlots];  // per axis: slot -> line base (line_slots), kEmptySlot if none
   double VA[3][kMaxN * kMaxN];  // (1/h_A) V: volume operator of axis A
   double xi[kMaxN];             // time nodes (initial guesses)
   float xif[kMaxN];
@@ -362,34 +363,71 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
     }
 }
 
+// Lines of an axis phase in slots: slot s of axis A holds the line whose
+// first node sits at P.sw->ls[A][s] (the slot tables of line_slots), so
+// that the lanes of a wavefront hit distinct LDS banks; n^D lines in
+// round64(n^D) slots.
+template <int D, int N>
+__host__ __device__ constexpr int line_slots_count() { return round64(ipow(N + 1, D)); }
+// Degrees whose slot tables differ from the plain line order by enough to
+// matter (from a model of the bank conflicts of each order: at n = 4 and
+// n = 8 no order of the lines removes them); the others use the plain
+// order, computed, and keep no table.
+template <int D, int N>
+__host__ __device__ constexpr bool slot_tables() {
+  return D == 3 ? (N == 2 || N == 4 || N == 5 || N == 6) : (N >= 3 && N <= 6);
+}
+// The predictor copies the slot tables of its problem into the first
+// slot_table_bytes of its LDS (the regions A and R follow them).
+template <int D, int N>
+__host__ __device__ constexpr size_t slot_table_bytes() {
+  return slot_tables<D, N>() ? round256((size_t)3 * line_slots_count<D, N>() * 2) : 0;
+}
+template <int D, int N, int A>
+__device__ __forceinline__ int slot_base(int s) {
+  if constexpr (slot_tables<D, N>()) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    return ((const uint16_t *)smem_raw)[A * line_slots_count<D, N>() + s];
+  } else {  // plain order: line s is (time slice s / NF, face index s % NF over the other axes)
+    using S = Shape<D, N>;
+    constexpr int ST = ipow(N + 1, A);
+    if (s >= S::ND) return kEmptySlot;
+    const int l0 = s / S::NF, r = s - l0 * S::NF;
+    return l0 * S::ND + r % ST + (r / ST) * ST * S::n;
+  }
+}
+
+// The axis that runs alone after the paired axes, adding to the first
+// accumulator: the one whose slot order leaves the fewest LDS bank
+// conflicts for its three accesses (read q, read and write the
+// accumulator), from a model of the slot tables (-1 in 2-D: no third axis).
+__host__ __device__ constexpr int third_axis(int D, int N) {
+  return D < 3 ? -1 : ((N == 3 || N == 5 || N == 7) ? 2 : 0);
+}
+
 // Right-hand side along axis A for all lines of the space-time element
-// (one thread per line, lines enumerated over (l0, the other spatial
-// indices)), accumulated onto the earlier axes (A > 0).
-// With kSplit (elasticity, BS = 2 * round64(lines)) the first half of the
-// block takes the velocity rows of every line and the second half the
+// (one thread per slot), stored (kAcc false) or accumulated onto the
+// earlier axes.  With kSplit (elasticity, BS = 2 * slots) the first half of
+// the block takes the velocity rows of every line and the second half the
 // stress rows (whole wavefronts on each side).
-template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kSplit = false>
+template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kSplit = false,
+          bool kAcc = (A > 0)>
 __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
-  using S = Shape<D, N>;
-  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
-  constexpr int ST = ipow(n, A);
+  constexpr int NS = line_slots_count<D, N>(), NST = Shape<D, N>::NST;
   if constexpr (kSplit) {
-    constexpr int H = round64(NST / n);
-    static_assert(BS == 2 * H && PDE::kElastic, "two threads per line");
-    const int half = threadIdx.x / H, L = threadIdx.x - half * H;
-    if (L < NST / n) {
-      const int l0 = L / NF, r = L - l0 * NF;
-      const int base = l0 * ND + r % ST + (r / ST) * ST * n;
+    static_assert(BS == 2 * NS && PDE::kElastic, "two threads per line");
+    const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
+    const int base = slot_base<D, N, A>(L);
+    if (base != kEmptySlot) {
       if (half == 0)
-        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0), 1>(P, sq, sacc, base, irho, lam, mu);
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc, 1>(P, sq, sacc, base, irho, lam, mu);
       else
-        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0), 2>(P, sq, sacc, base, irho, lam, mu);
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc, 2>(P, sq, sacc, base, irho, lam, mu);
     }
   } else {
-    for (int L = threadIdx.x; L < NST / n; L += BS) {
-      const int l0 = L / NF, r = L - l0 * NF;
-      const int base = l0 * ND + r % ST + (r / ST) * ST * n;
-      line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, (A > 0)>(P, sq, sacc, base, irho, lam, mu);
+    for (int L = threadIdx.x; L < NS; L += BS) {
+      const int base = slot_base<D, N, A>(L);
+      if (base != kEmptySlot) line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc>(P, sq, sacc, base, irho, lam, mu);
     }
   }
 }
@@ -512,65 +550,70 @@ __device__ __forceinline__ void gather_parts(const T *part, T (&out)[TimeItems<D
 }
 
 // Whether a block of BS threads holds the lines of two axes at once, each
-// set on its own half of whole wavefronts (one thread per line).
+// set on its own half of whole wavefronts (one thread per slot).
 template <int D, int N, int BS>
 __host__ __device__ constexpr bool pair_axes() {
   return D >= 2 && BS >= 2 * round64(ipow(N + 1, D));
 }
+// The two axes of the pair: the ones other than third_axis (0 and 1 in 2-D).
+template <int D, int N>
+__host__ __device__ constexpr int pair_a() { return third_axis(D, N) == 0 ? 1 : 0; }
+template <int D, int N>
+__host__ __device__ constexpr int pair_b() { return third_axis(D, N) == 2 || D < 3 ? 1 : 2; }
 
-// Axes 0 and 1 at the same time: the first half of the block stores the
-// lines of axis 0 into sacc, the second half those of axis 1 into sacc2
-// (the time phase adds the two).
+// The paired axes at the same time: the first half of the block stores the
+// lines of axis pair_a into sacc, the second half those of axis pair_b into
+// sacc2 (the time phase adds the two).
 template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS>
-__device__ __forceinline__ void rhs_axes01(PArg &P, const TQ *sq, T *sacc, T *sacc2, T irho, T lam, T mu) {
-  using S = Shape<D, N>;
-  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
-  constexpr int H = round64(NST / n);
+__device__ __forceinline__ void rhs_pair(PArg &P, const TQ *sq, T *sacc, T *sacc2, T irho, T lam, T mu) {
+  constexpr int NS = line_slots_count<D, N>(), NST = Shape<D, N>::NST;
+  constexpr int a = pair_a<D, N>(), b = pair_b<D, N>();
   static_assert(pair_axes<D, N, BS>(), "two halves of whole wavefronts");
-  const int half = threadIdx.x / H, L = threadIdx.x - half * H;
-  if (L < NST / n) {
-    const int l0 = L / NF, r = L - l0 * NF;
-    if (half == 0)
-      line_rhs<D, N, PDE, 0, T, TQ, kRoundBF, NST, false>(P, sq, sacc, l0 * ND + r * n, irho, lam, mu);
-    else if (half == 1)
-      line_rhs<D, N, PDE, 1, T, TQ, kRoundBF, NST, false>(P, sq, sacc2, l0 * ND + r % n + (r / n) * n * n, irho,
-                                                          lam, mu);
+  const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
+  if (half == 0) {
+    const int base = slot_base<D, N, a>(L);
+    if (base != kEmptySlot) line_rhs<D, N, PDE, a, T, TQ, kRoundBF, NST, false>(P, sq, sacc, base, irho, lam, mu);
+  } else if (half == 1) {
+    const int base = slot_base<D, N, b>(L);
+    if (base != kEmptySlot) line_rhs<D, N, PDE, b, T, TQ, kRoundBF, NST, false>(P, sq, sacc2, base, irho, lam, mu);
   }
 }
 
-// Axes 0 and 1 at the same time with one accumulator: the first half of
-// the block stores the lines of axis 0 into sacc while the second half
-// computes those of axis 1 into registers, and adds them after a barrier
-// (used where region R has no room for a second accumulator).
+// The paired axes with one accumulator: the first half of the block stores
+// the lines of axis pair_a into sacc while the second half computes those of
+// axis pair_b into registers, and adds them after a barrier (used where
+// region R has no room for a second accumulator).
 template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS>
-__device__ __forceinline__ void rhs_axes01_held(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
+__device__ __forceinline__ void rhs_pair_held(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
-  constexpr int H = round64(NST / n);
+  constexpr int n = S::n, M = PDE::M, NST = S::NST;
+  constexpr int NS = line_slots_count<D, N>();
+  constexpr int a = pair_a<D, N>(), b = pair_b<D, N>();
+  constexpr int STb = ipow(n, b);
   static_assert(pair_axes<D, N, BS>(), "two halves of whole wavefronts");
-  const int half = threadIdx.x / H, L = threadIdx.x - half * H;
-  const bool active = L < NST / n;
-  const int l0 = L / NF, r = L - l0 * NF;
-  const int base1 = l0 * ND + r % n + (r / n) * n * n;
+  const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
+  const int base = half == 0 ? slot_base<D, N, a>(L) : (half == 1 ? slot_base<D, N, b>(L) : (int)kEmptySlot);
+  const bool active = base != kEmptySlot;
   T held[n * M];
   if (active) {
     if (half == 0)
-      line_rhs<D, N, PDE, 0, T, TQ, kRoundBF, NST, false>(P, sq, sacc, l0 * ND + r * n, irho, lam, mu);
-    else if (half == 1)
-      line_rhs<D, N, PDE, 1, T, TQ, kRoundBF, NST, false, 0, 0, true>(P, sq, sacc, base1, irho, lam, mu, held);
+      line_rhs<D, N, PDE, a, T, TQ, kRoundBF, NST, false>(P, sq, sacc, base, irho, lam, mu);
+    else
+      line_rhs<D, N, PDE, b, T, TQ, kRoundBF, NST, false, 0, 0, true>(P, sq, sacc, base, irho, lam, mu, held);
   }
   __syncthreads();
   if (active && half == 1)
 #pragma unroll
     for (int k = 0; k < n; k++)
 #pragma unroll
-      for (int v = 0; v < M; v++) sacc[v * NST + base1 + k * n] += held[k * M + v];
+      for (int v = 0; v < M; v++) sacc[v * NST + base + k * STb] += held[k * M + v];
 }
 
 // One Picard sweep: R(q) over all axes, then the time contraction.  With
-// kPair (pair_axes) axes 0 and 1 run at the same time: kPairTwo with a
-// second accumulator sacc2 of M NST values, kPairHeld with the axis-1
-// results held in registers; axis 2 then accumulates onto sacc.
+// kPair (pair_axes) the axes pair_a and pair_b run at the same time:
+// kPairTwo with a second accumulator sacc2 of M NST values, kPairHeld with
+// the pair_b results held in registers; third_axis then accumulates onto
+// sacc.
 constexpr int kPairTwo = 1, kPairHeld = 2;
 template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false,
           int kPair = 0>
@@ -579,12 +622,12 @@ __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO 
   if constexpr (kPair != 0) {
     static_assert(!kSplit, "one thread per line");
     if constexpr (kPair == kPairTwo)
-      rhs_axes01<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
+      rhs_pair<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
     else
-      rhs_axes01_held<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+      rhs_pair_held<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 2) {
-      rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
+      rhs_axis<D, N, PDE, third_axis(D, N), T, TQ, kRoundBF, BS, false, true>(P, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
     time_phase<D, N, PDE, T, TO, BS, kPair == kPairTwo>(P, sacc, qout, ureg, dt, sacc2);
@@ -611,12 +654,11 @@ template <int D, int N, class PDE, int A, int kPart, int kShift, int BS>
 __device__ __forceinline__ void rhs_axis_group(PArg &P, const double *sq, double *sacc, double irho, double lam,
                                                double mu) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, ND = S::ND, NST = S::NST, NF = S::NF;
-  constexpr int ST = ipow(n, A);
-  for (int L = threadIdx.x; L < NST / n; L += BS) {
-    const int l0 = L / NF, r = L - l0 * NF;
-    const int base = l0 * ND + r % ST + (r / ST) * ST * n;
-    line_rhs<D, N, PDE, A, double, double, false, NST, (A > 0), kPart, kShift>(P, sq, sacc, base, irho, lam, mu);
+  constexpr int NST = S::NST, NS = line_slots_count<D, N>();
+  for (int L = threadIdx.x; L < NS; L += BS) {
+    const int base = slot_base<D, N, A>(L);
+    if (base != kEmptySlot)
+      line_rhs<D, N, PDE, A, double, double, false, NST, (A > 0), kPart, kShift>(P, sq, sacc, base, irho, lam, mu);
   }
 }
 
@@ -791,13 +833,6 @@ typedef float f4v __attribute__((ext_vector_type(4)));
 __host__ __device__ constexpr int mfma_groups(int n) { return (n == 5 || n == 6) ? 1 : (n + 3) / 4; }
 __host__ __device__ constexpr int mfma_valu_rows(int n) { return n - 4 * mfma_groups(n) > 0 ? n - 4 * mfma_groups(n) : 0; }
 
-template <int D, int N>
-__device__ __forceinline__ int line_base(int line, int ST) {
-  using S = Shape<D, N>;
-  const int l0 = line / S::NF, r = line - l0 * S::NF;
-  return l0 * S::ND + (r % ST) + (r / ST) * ST * S::n;
-}
-
 // MFMA operands of a lane, loaded once per element: rows 4c + (lane & 3) of
 // the unscaled Dhat (zero past row n-1) and of (-dt/h_0) T (Euler) or dt T
 // (elasticity).  The Euler sweeps
@@ -837,11 +872,11 @@ __device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const f
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, NST = S::NST;
   constexpr int ST = ipow(n, A);
-  constexpr int NL = NST / n;
   constexpr int G = mfma_groups(n), VR = mfma_valu_rows(n);
   const int lane = threadIdx.x & 63;
-  const bool own = L0 + lane < NL;
-  const int base = line_base<D, N>(own ? L0 + lane : L0, ST);
+  const int sb = slot_base<D, N, A>(L0 + lane);
+  const bool own = sb != kEmptySlot;
+  const int base = own ? sb : 0;  // an empty slot computes on line 0 and stores nothing
   float X[n][M];
   // Euler: flux scale h_0/h_A (1 on cubic elements: no multiply)
   const float fs = (float)(P.g.inv_h[A] / P.g.inv_h[0]);
@@ -914,9 +949,9 @@ __device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const f
 template <int D, int N, class PDE, int A, bool kAcc, int WAVES, int W0 = 0>
 __device__ __forceinline__ void mfma_axis(PArg &P, const MfmaOps<N> &o, const float *sq, float *sacc, float irho,
                                           float lam, float mu) {
-  constexpr int NL = Shape<D, N>::NST / (N + 1);
+  constexpr int NS = line_slots_count<D, N>();
   const int wave = (threadIdx.x >> 6) - W0;
-  for (int L0 = wave * 64; L0 < NL; L0 += WAVES * 64)
+  for (int L0 = wave * 64; L0 < NS; L0 += WAVES * 64)
     mfma_lines<D, N, PDE, A, kAcc>(P, o, sq, sacc, L0, irho, lam, mu);
 }
 
@@ -968,8 +1003,9 @@ __device__ __forceinline__ void mfma_time(PArg &P, const MfmaOps<N> &o, const fl
 }
 
 // One FP32 Picard sweep with MFMA contractions.  With pair_axes the lines
-// of axes 0 and 1 run at the same time on the two halves of the block into
-// two accumulators (as rhs_axes01); axis 2 then accumulates onto the first.
+// of axes pair_a and pair_b run at the same time on the two halves of the
+// block into two accumulators (as rhs_pair); third_axis then accumulates
+// onto the first.
 template <int D, int N, class PDE, int BS>
 __device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, float *sq, float *sacc, float *sacc2,
                                                   const double *ureg, float dt, float irho, float lam, float mu) {
@@ -978,10 +1014,14 @@ __device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, 
   if constexpr (kPair) {
     constexpr int HW = round64(ipow(N + 1, D)) / 64;  // wavefronts per half
     if ((int)(threadIdx.x >> 6) < HW)
-      mfma_axis<D, N, PDE, 0, false, HW, 0>(P, o, sq, sacc, irho, lam, mu);
+      mfma_axis<D, N, PDE, pair_a<D, N>(), false, HW, 0>(P, o, sq, sacc, irho, lam, mu);
     else if ((int)(threadIdx.x >> 6) < 2 * HW)
-      mfma_axis<D, N, PDE, 1, false, HW, HW>(P, o, sq, sacc2, irho, lam, mu);
+      mfma_axis<D, N, PDE, pair_b<D, N>(), false, HW, HW>(P, o, sq, sacc2, irho, lam, mu);
     __syncthreads();
+    if constexpr (D > 2) {
+      mfma_axis<D, N, PDE, third_axis(D, N), true, NW>(P, o, sq, sacc, irho, lam, mu);
+      __syncthreads();
+    }
   } else {
     mfma_axis<D, N, PDE, 0, false, NW>(P, o, sq, sacc, irho, lam, mu);
     __syncthreads();
@@ -989,10 +1029,10 @@ __device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, 
       mfma_axis<D, N, PDE, 1, true, NW>(P, o, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
-  }
-  if constexpr (D > 2) {
-    mfma_axis<D, N, PDE, 2, true, NW>(P, o, sq, sacc, irho, lam, mu);
-    __syncthreads();
+    if constexpr (D > 2) {
+      mfma_axis<D, N, PDE, 2, true, NW>(P, o, sq, sacc, irho, lam, mu);
+      __syncthreads();
+    }
   }
   mfma_time<D, N, PDE, BS, kPair>(P, o, sacc, sacc2, sq, ureg, dt);
   __syncthreads();
@@ -1466,24 +1506,31 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
 // index of the element phases live across iterations and cost occupancy, so
 // each workgroup takes a single element.  u, dt and the optional q-hat output
 // are the call's buffers (per-problem offsets in the record).
-// Waves per SIMD the register allocation must allow: as many as the LDS of
-// the FP32 MFMA variants lets reside (their matrix accumulators would
-// otherwise push the allocation past it); 1 (no constraint) for the others.
-template <int D, int N, int M, int PREC, bool kMfma, int kBFac>
+// Dynamic LDS bytes of a predictor variant: the slot tables, region A and
+// region R (or G for the FP64 row-group sweeps; only A when the FP64
+// accumulator lives in HBM).
+template <int D, int N, int M, int PREC, bool kAccLds, int kBFac>
+__host__ __device__ constexpr size_t pred_lds_bytes() {
+  return slot_table_bytes<D, N>() +
+         ((PREC == kFP64 && !kAccLds) ? PredLds<D, N, M, PREC>::A
+          : (kBFac == kRowGroups ? PredLds<D, N, M, PREC>::A + PredLds<D, N, M, PREC>::G
+                                 : PredLds<D, N, M, PREC>::A + PredLds<D, N, M, PREC>::R));
+}
+
+// Waves per SIMD the register allocation must allow: as many as the LDS
+// footprint lets reside (more registers than that would cost occupancy the
+// LDS leaves room for).
+template <int D, int N, int M, int PREC, bool kAccLds, int kBFac>
 __host__ __device__ constexpr int pred_waves_per_eu() {
-  if constexpr (!kMfma) {
-    return 1;
-  } else {
-    constexpr size_t lds = PredLds<D, N, M, PREC>::A + PredLds<D, N, M, PREC>::R;
-    constexpr int blocks = (int)((160u * 1024u) / lds);
-    constexpr int w = blocks * pred_block(D, N, kBFac) / 64 / 4;
-    return w < 1 ? 1 : (w > 8 ? 8 : w);
-  }
+  constexpr size_t lds = pred_lds_bytes<D, N, M, PREC, kAccLds, kBFac>();
+  constexpr int blocks = (int)((160u * 1024u) / lds);
+  constexpr int w = blocks * pred_block(D, N, kBFac) / 64 / 4;
+  return w < 1 ? 1 : (w > 4 ? 4 : w);  // at most 4: small elements keep 128 registers
 }
 
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
 __global__ void __launch_bounds__(pred_block(D, N, kBFac))
-    __attribute__((amdgpu_waves_per_eu(pred_waves_per_eu<D, N, PDE::M, PREC, kMfma, kBFac>())))
+    __attribute__((amdgpu_waves_per_eu(pred_waves_per_eu<D, N, PDE::M, PREC, kAccLds, kBFac>())))
     k_predictor(const PredArgs *args, const Batch b, const double *u, const double *dt, double *qhat) {
   constexpr int M = PDE::M, ND = Shape<D, N>::ND, NST = Shape<D, N>::NST;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -1493,7 +1540,15 @@ __global__ void __launch_bounds__(pred_block(D, N, kBFac))
   const int64_t e = tile - cload(&b.start[p]);
   const double *ue = u + P.u_off + e * (int64_t)(M * ND);
   double *qo = qhat ? qhat + P.q_off + e * (int64_t)(M * NST) : nullptr;
-  predictor_element<D, N, PDE, PREC, kAccLds, kMfma, kBFac>(P, e, ue, cload(&dt[P.pidx]), qo, smem_raw);
+  // slot tables of the line phases into the head of the LDS (read by
+  // slot_base; the element's staging ends with a barrier before any line
+  // phase)
+  constexpr int NS = line_slots_count<D, N>();
+  if constexpr (slot_tables<D, N>())
+    for (int i = threadIdx.x; i < 3 * NS; i += pred_block(D, N, kBFac))
+      ((uint16_t *)smem_raw)[i] = P.sw->ls[i / NS][i - (i / NS) * NS];
+  predictor_element<D, N, PDE, PREC, kAccLds, kMfma, kBFac>(P, e, ue, cload(&dt[P.pidx]), qo,
+                                                            smem_raw + slot_table_bytes<D, N>());
 }
 
 // ------------------------------------------------------------ faces

@@ -787,6 +787,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       s.sw.Dhf[k] = (float)s.ops.D[k];
       for (int a = 0; a < 3; a++) s.sw.VA[a][k] = s.g.inv_h[a] * s.ops.V[k];
     }
+    for (int a = 0; a < 3; a++) line_slots(s.D, s.N, a < s.D ? a : 0, s.sw.ls[a]);
     for (int k = 0; k < kMaxN; k++) {
       s.sw.Trow[k] = s.ops.Trow[k];
       s.sw.Trowf[k] = (float)s.ops.Trow[k];

@@ -185,4 +185,34 @@ double stability_alpha(int N) {
   return (N >= 0 && N < kMaxN) ? a[N] : -1.0;
 }
 
+void line_slots(int D, int N, int A, uint16_t *out) {
+  const int n = N + 1;
+  int nd = 1;
+  for (int a = 0; a < D; a++) nd *= n;
+  const int nf = nd / n, nl = nd;  // lines of one axis phase: n time slices x n^(D-1)
+  int st = 1;
+  for (int a = 0; a < A; a++) st *= n;
+  const int waves = (nl + 63) / 64;
+  for (int s = 0; s < kMaxSlots; s++) out[s] = kEmptySlot;
+  // line L: time slice l0 = L / nf, face index r = L % nf over the other axes
+  int rest[kMaxSlots], nrest = nl;
+  for (int L = 0; L < nl; L++) {
+    const int l0 = L / nf, r = L % nf;
+    rest[L] = l0 * nd + r % st + (r / st) * st * n;
+  }
+  for (int w = 0; w < waves; w++) {
+    int keep = 0;
+    for (int i = 0; i < nrest; i++) {
+      const int b = rest[i], s = w * 64 + b % 64;
+      if (out[s] == kEmptySlot) out[s] = (uint16_t)b;
+      else rest[keep++] = b;
+    }
+    nrest = keep;
+  }
+  for (int i = 0, s = 0; i < nrest; i++) {  // lines left over: first free slots
+    while (out[s] != kEmptySlot) s++;
+    out[s] = (uint16_t)rest[i];
+  }
+}
+
 }  // namespace ader

@@ -33,11 +33,10 @@ struct KernelSet {
 
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
 void add_variant(KernelSet &k, const char *name) {
-  using L = PredLds<D, N, PDE::M, PREC>;
   PredVariant v;
   v.fn = (const void *)&k_predictor<D, N, PDE, PREC, kAccLds, kMfma, kBFac>;
   v.threads = pred_block(D, N, kBFac);
-  v.lds = (PREC == kFP64 && !kAccLds) ? L::A : (kBFac == kRowGroups ? L::A + L::G : L::A + L::R);
+  v.lds = pred_lds_bytes<D, N, PDE::M, PREC, kAccLds, kBFac>();
   v.prec = PREC;
   v.acc_lds = kAccLds;
   v.mfma = kMfma;
