@@ -68,6 +68,10 @@ def lib():
                                              C.c_double, C.c_int, _DP]
         L.orc_corrector.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP]
         L.orc_step.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP]
+        L.orc_predictor_hist.argtypes = [C.POINTER(_Problem), _DP, C.c_double, _DP, C.c_double, _DP]
+        L.orc_guess_hist.argtypes = [C.POINTER(_Problem), _DP, C.c_double, _DP, C.c_double, _DP]
+        L.orc_step_hist.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_double, _DP, _DP, _DP,
+                                    C.POINTER(C.c_int)]
         L.orc_totals.argtypes = [C.POINTER(_Problem), _DP, _DP]
         L.orc_detect.argtypes = [C.POINTER(_Problem), _DP, _DP, C.c_void_p]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -208,11 +212,45 @@ def step(prob, u: np.ndarray, t: float, t_end: float):
     return u, tt.value, dt.value
 
 
+def predictor_hist(prob, u: np.ndarray, dt: float, qprev=None, dtprev: float = 0.0,
+                   guess_only: bool = False) -> np.ndarray:
+    """Predictor (or, with guess_only, its initial guess alone) with the
+    previous interval's predictor qprev[E][m][n][n^d] of step dtprev (guess 3)."""
+    b = _Bound(prob)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    q = np.zeros((b.E, b.m, b.n, b.nd))
+    qp = None if qprev is None else np.ascontiguousarray(qprev, dtype=np.float64)
+    f = lib().orc_guess_hist if guess_only else lib().orc_predictor_hist
+    assert f(b.ref, _ptr(u), float(dt), None if qp is None else _ptr(qp), float(dtprev), _ptr(q)) == 0
+    return q
+
+
+def step_hist(prob, u: np.ndarray, t: float, t_end: float, hist=None):
+    """One step that carries the previous interval (guess 3): hist is None
+    or (qprev, dtprev) from the step before; returns (u_new, t_new, dt, hist)."""
+    b = _Bound(prob)
+    u = np.array(u, dtype=np.float64, order="C", copy=True)
+    if hist is None:
+        qprev, dtp, has = np.zeros((b.E, b.m, b.n, b.nd)), C.c_double(0.0), C.c_int(0)
+    else:
+        qprev, dtp, has = np.array(hist[0], dtype=np.float64, order="C", copy=True), C.c_double(hist[1]), C.c_int(1)
+    tt = C.c_double(t)
+    dt = C.c_double(0.0)
+    rc = lib().orc_step_hist(b.ref, _ptr(u), C.byref(tt), float(t_end), C.byref(dt), _ptr(qprev), C.byref(dtp),
+                             C.byref(has))
+    if rc != 0:
+        raise FloatingPointError("oracle: non-physical or non-finite state")
+    return u, tt.value, dt.value, (qprev, dtp.value)
+
+
 def run(prob, u: np.ndarray, t0: float, t_end: float, max_steps: int = 1 << 30):
     """Steps until t_end or max_steps; returns (u, t, steps)."""
-    t, steps = t0, 0
+    t, steps, hist = t0, 0, None
     while t < t_end and steps < max_steps:
-        u, t, _ = step(prob, u, t, t_end)
+        if int(getattr(prob, "guess", 0) or 0) == 3:
+            u, t, _, hist = step_hist(prob, u, t, t_end, hist)
+        else:
+            u, t, _ = step(prob, u, t, t_end)
         steps += 1
     return u, t, steps
 

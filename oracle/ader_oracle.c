@@ -238,7 +238,7 @@ typedef struct {
 
 static int setup(const orc_problem *p, setup_t *s) {
   if (p->dim < 1 || p->dim > 3 || p->N < 0 || p->N + 1 > ORC_MAXN) return -1;
-  if (p->guess < 0 || p->guess > 2) return -1;
+  if (p->guess < 0 || p->guess > 3) return -1;
   if (p->pde == ORC_ELASTIC && (p->dim != 3 || !p->material)) return -1;
   s->d = p->dim;
   s->n = p->N + 1;
@@ -417,6 +417,7 @@ static void rhs_of_state(const orc_problem *p, const setup_t *s, const double *m
 
 int orc_sweeps(const orc_problem *p) {
   if (p->picard > 0) return p->picard;
+  if (p->guess == 3) return 1;
   int g = p->guess > 0 ? p->guess : 0;
   return p->N + 1 - g > 1 ? p->N + 1 - g : 1;
 }
@@ -428,9 +429,24 @@ int orc_sweeps(const orc_problem *p) {
  * done; stops early only when tol > 0 and the update fell to tol * max|q|. */
 static int element_predictor(const orc_problem *p, const setup_t *s, const double *mat,
                              const double *ue, double dt, int sweeps, double tol,
-                             double *q, double *F, double *R) {
+                             double *q, double *F, double *R, const double *qprev, double ratio) {
   int m = s->m, nd = s->nd, n = s->n;
-  if (p->guess == 0) {
+  if (p->guess == 3 && qprev) {
+    /* the previous interval's polynomial q_h^{n-1}(tau), tau in [0,1] on
+     * [t^{n-1}, t^n], evaluated at the new time nodes t^n + xi_l dt, i.e.
+     * tau = 1 + xi_l dt/dt_prev, minus its value at tau = 1 */
+    for (int v = 0; v < m; v++)
+      for (int l0 = 0; l0 < n; l0++) {
+        const double tau = 1.0 + s->xi[l0] * ratio;
+        for (int k = 0; k < nd; k++) {
+          double g = ue[v * nd + k];
+          for (int j = 0; j < n; j++)
+            g += qprev[(v * n + j) * nd + k] *
+                 (orc_lagrange(n, s->xi, j, tau) - orc_lagrange(n, s->xi, j, 1.0));
+          q[(v * n + l0) * nd + k] = g;
+        }
+      }
+  } else if (p->guess == 0 || p->guess == 3) {
     for (int v = 0; v < m; v++)
       for (int l0 = 0; l0 < n; l0++)
         for (int k = 0; k < nd; k++) q[(v * n + l0) * nd + k] = ue[v * nd + k];
@@ -473,7 +489,7 @@ static int element_predictor(const orc_problem *p, const setup_t *s, const doubl
 }
 
 static int run_predictor(const orc_problem *p, const double *u, double dt, int sweeps,
-                         double tol, double *qhat) {
+                         double tol, double *qhat, const double *qprev, double ratio) {
   setup_t s;
   if (setup(p, &s)) return -1;
   int maxused = 0, fail = 0;
@@ -489,7 +505,8 @@ static int run_predictor(const orc_problem *p, const double *u, double dt, int s
 #pragma omp for schedule(static)
       for (int e = 0; e < s.E; e++) {
         int used = element_predictor(p, &s, elem_mat(p, e), u + (size_t)e * s.m * s.nd, dt,
-                                     sweeps, tol, qhat + (size_t)e * s.m * s.nst, F, R);
+                                     sweeps, tol, qhat + (size_t)e * s.m * s.nst, F, R,
+                                     qprev ? qprev + (size_t)e * s.m * s.nst : NULL, ratio);
         if (used > used_local) used_local = used;
       }
     }
@@ -502,13 +519,26 @@ static int run_predictor(const orc_problem *p, const double *u, double dt, int s
 }
 
 int orc_predictor(const orc_problem *p, const double *u, double dt, double *qhat) {
-  int sweeps = orc_sweeps(p);
-  return run_predictor(p, u, dt, sweeps, 0.0, qhat) < 0 ? -1 : 0;
+  return orc_predictor_hist(p, u, dt, NULL, 0.0, qhat);
+}
+
+int orc_guess_hist(const orc_problem *p, const double *u, double dt, const double *qprev, double dtprev,
+                   double *q0) {
+  const int hist = p->guess == 3 && qprev && dtprev > 0.0;
+  return run_predictor(p, u, dt, 0, 0.0, q0, hist ? qprev : NULL, hist ? dt / dtprev : 0.0) < 0 ? -1 : 0;
+}
+
+int orc_predictor_hist(const orc_problem *p, const double *u, double dt, const double *qprev,
+                       double dtprev, double *qhat) {
+  const int hist = p->guess == 3 && qprev && dtprev > 0.0;
+  /* guess 3 without a previous interval: the plain scheme (constant guess, N+1 sweeps) */
+  const int sweeps = (p->guess == 3 && !hist) ? p->N + 1 : orc_sweeps(p);
+  return run_predictor(p, u, dt, sweeps, 0.0, qhat, hist ? qprev : NULL, hist ? dt / dtprev : 0.0) < 0 ? -1 : 0;
 }
 
 int orc_predictor_converge(const orc_problem *p, const double *u, double dt, double tol,
                            int max_sweeps, double *qhat) {
-  return run_predictor(p, u, dt, max_sweeps, tol, qhat);
+  return run_predictor(p, u, dt, max_sweeps, tol, qhat, NULL, 0.0);
 }
 
 /* ------------------------------------------------------------------ */
@@ -715,6 +745,11 @@ double orc_cfl_dt(const orc_problem *p, const double *u) {
 }
 
 int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *dt_out) {
+  return orc_step_hist(p, u, t, t_end, dt_out, NULL, NULL, NULL);
+}
+
+int orc_step_hist(const orc_problem *p, double *u, double *t, double t_end, double *dt_out, double *qprev,
+                  double *dtprev, int *has) {
   setup_t s;
   if (setup(p, &s)) return -1;
   double dt = orc_cfl_dt(p, u);
@@ -731,10 +766,17 @@ int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *d
   double *qhat = malloc(sizeof(double) * nq);
   double *un = malloc(sizeof(double) * nu);
   int rc = -1;
-  if (qhat && un && orc_predictor(p, u, dt, qhat) == 0 && orc_corrector(p, u, qhat, dt, un) == 0) {
+  const int hist = qprev && dtprev && has && *has;
+  if (qhat && un && orc_predictor_hist(p, u, dt, hist ? qprev : NULL, hist ? *dtprev : 0.0, qhat) == 0 &&
+      orc_corrector(p, u, qhat, dt, un) == 0) {
     memcpy(u, un, sizeof(double) * nu);
     *t = tn;
     if (dt_out) *dt_out = dt;
+    if (qprev && dtprev && has) {  /* this interval becomes the previous one */
+      memcpy(qprev, qhat, sizeof(double) * nq);
+      *dtprev = dt;
+      *has = 1;
+    }
     rc = 0;
   }
   free(qhat);

@@ -43,7 +43,7 @@ typedef struct {
   int pde;          /* ORC_EULER or ORC_ELASTIC */
   double gamma;     /* Euler: ratio of specific heats */
   const double *material; /* ELASTIC: [E][3] = (rho, lambda, mu) */
-  int picard;       /* number of Picard sweeps; 0 -> max(1, N+1-guess) */
+  int picard;       /* number of Picard sweeps; 0 -> max(1, N+1-guess), 1 for guess 3 */
   double cfl;       /* dt = cfl*alpha_N / max_e sum_d lambda_d/h_d */
   int guess;        /* initial guess of the Picard iteration (Sec. 2.2):
                        0  q0 = u_h(t^n), constant in time;
@@ -52,11 +52,19 @@ typedef struct {
                        2  third-order Taylor type
                           q0(t) = u + (t - t^n) k1 + (t - t^n)^2 (k2 - k1) / (2 dt),
                           k1 = L(u), k2 = L(u + dt k1);
+                       3  extrapolation of the previous interval's predictor
+                          q_h^{n-1} (a polynomial of degree N in time on
+                          [t^{n-1}, t^n]) into [t^n, t^{n+1}], shifted to start
+                          at the corrected state:
+                          q0(t) = u + q_h^{n-1}(t) - q_h^{n-1}(t^n);
+                          without a previous interval (the first step) the
+                          constant guess with N+1 sweeps;
                        L = S - div F - B.grad, the collocated right-hand side. */
   int face_avg;     /* face integrals from time-averaged traces (see orc_corrector) */
 } orc_problem;
 
-/* Picard sweeps used for a problem: picard, or max(1, N+1-guess). */
+/* Picard sweeps used for a problem: picard, or max(1, N+1-guess), or 1 for
+ * guess 3 (with a previous interval; N+1 without one). */
 int orc_sweeps(const orc_problem *p);
 
 /* A posteriori detection of troubled elements (Sec. 2.3: the checks that
@@ -112,6 +120,20 @@ int orc_corrector(const orc_problem *p, const double *u, const double *qhat,
 /* One full step with dt = min(cfl dt, t_end - t); updates u and *t in place.
  * Returns 0, or -1 on a non-physical state. *dt_out may be NULL. */
 int orc_step(const orc_problem *p, double *u, double *t, double t_end, double *dt_out);
+/* Predictor with the previous interval's predictor qprev ([E][m][n][n^d],
+ * step dtprev) for guess 3; qprev = NULL or dtprev <= 0: no previous
+ * interval (constant guess, N+1 sweeps). */
+int orc_predictor_hist(const orc_problem *p, const double *u, double dt, const double *qprev,
+                       double dtprev, double *qhat);
+/* The initial guess alone (no sweep), with the previous interval as in
+ * orc_predictor_hist; q0 is [E][m][n][n^d]. */
+int orc_guess_hist(const orc_problem *p, const double *u, double dt, const double *qprev, double dtprev,
+                   double *q0);
+/* orc_step that carries the previous interval for guess 3: qprev
+ * ([E][m][n][n^d]) and *dtprev hold it when *has is set; on return they hold
+ * this step's predictor and step, and *has is set. */
+int orc_step_hist(const orc_problem *p, double *u, double *t, double t_end, double *dt_out, double *qprev,
+                  double *dtprev, int *has);
 /* Integral of every variable over the domain (Neumaier summation): sums[m]. */
 int orc_totals(const orc_problem *p, const double *u, double *sums);
 /* Threads the OpenMP runtime will use. */
