@@ -102,7 +102,8 @@ def predictor_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False, 
       time node) and 2 flops per space-time value, then sweeps-1 full
       sweeps; guess 1 (2) takes one (two) such slice right-hand sides, 2
       flops per node value for u + dt k1 (guess 2) and 3 (5) flops per
-      space-time value for the Taylor polynomial, then `sweeps` full sweeps.
+      space-time value for the Taylor polynomial, then `sweeps` full sweeps;
+      guess 3 evaluates N Taylor terms per space-time value (2N flops).
     Outputs (Euler): one more flux evaluation, the time average (2 flops per
       output and axis), the volume contraction (2n per output and axis),
       u* = u + dt V and the 2d face traces (2n per trace value); elasticity:
@@ -121,6 +122,8 @@ def predictor_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False, 
         outputs = 2 * n * m * nd + d * (2 * n * m * nd + cB * nd) + 2 * m * nd + 2 * d * 2 * n * m * nd
     if guess == 0:
         start, full = slice_rhs + 2 * m * nst, sweeps - 1
+    elif guess == 3:  # the Taylor polynomial of the previous interval at the time nodes
+        start, full = 2 * N * m * nst, sweeps
     elif guess == 1:
         start, full = slice_rhs + 3 * m * nst, sweeps
     else:
@@ -129,8 +132,11 @@ def predictor_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False, 
 
 
 def sweeps_of(p) -> int:
-    """Picard sweeps of a problem: picard, or max(1, N+1-guess)."""
-    return p.picard or max(1, p.N + 1 - (p.guess or 0))
+    """Picard sweeps of a problem: picard, or max(1, N+1-guess), or 1 for
+    the extrapolation guess (3)."""
+    if p.picard:
+        return p.picard
+    return 1 if (p.guess or 0) == 3 else max(1, p.N + 1 - (p.guess or 0))
 
 
 def step_bytes(d: int, N: int, m: int, trace_bytes: int = 8, face_avg: bool = False) -> dict:
@@ -546,8 +552,9 @@ def main():
     ap.add_argument("--nel", type=int, default=0, help="elements per axis (0: the workload's)")
     ap.add_argument("--degree", type=int, default=-1, help="degree N (-1: the workload's)")
     ap.add_argument("--picard", type=int, default=0, help="Picard sweeps (0: max(1, N+1-guess))")
-    ap.add_argument("--guess", type=int, default=0, choices=[0, 1, 2],
-                    help="initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type")
+    ap.add_argument("--guess", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type, "
+                         "3 extrapolation of the previous interval")
     ap.add_argument("--graph-steps", type=int, default=-1,
                     help="steps per captured-graph replay (0: plain ader_step; -1: 10 for batched, else 0)")
     ap.add_argument("--detect", action="store_true",
@@ -646,24 +653,31 @@ def main():
     if (args.guess == 0 and args.picard == 0 and args.prec != "fp64" and args.workload != "batched"
             and not args.no_guess_run):
         # the paper quotes its own cost per DOF update with an initial guess (Sec. 2.2): the same
-        # workload with the third-order Taylor-type guess and max(1, N+1-2) sweeps, both paths
-        kw2 = dict(kw, guess=2)
-        ref2, head2, l2g, _ = run_pair(args.workload, args.prec, args.steps, args.warmup, I, ader, torch, kw2)
-        line["initial_guess_run"] = {
-            "initial_guess": 2,
-            "picard_sweeps": sweeps_of(head2["prob"]),
-            "value": head2["value"],
-            "ms_per_step": head2["elapsed"] / args.steps * 1e3,
-            "fp64_value": ref2["value"],
-            "speedup_vs_fp64": head2["value"] / ref2["value"],
-            "rel_l2_vs_fp64_path": max(l2g),
-            "roofline": roof(head2, args.prec),
-            "state_finite": head2["finite"],
-            "note": "same workload, q0 from the third-order Taylor-type initial guess (k1, k2 from two "
-                    "one-slice right-hand sides), fewer Picard sweeps; error against the FP64 path "
-                    "run with the same guess",
-        }
-        del ref2, head2
+        # workload with the third-order Taylor-type guess (max(1, N-1) sweeps) and with the
+        # extrapolation of the previous interval (one sweep), both paths
+        notes = {2: "q0 from the third-order Taylor-type initial guess (k1, k2 from two one-slice "
+                    "right-hand sides), max(1, N-1) Picard sweeps",
+                 3: "q0 extrapolated from the previous interval's predictor, one Picard sweep (the "
+                    "first step of each run has no previous interval: constant guess, N+1 sweeps)"}
+        runs = {}
+        for g in (2, 3):
+            kw2 = dict(kw, guess=g)
+            ref2, head2, l2g, _ = run_pair(args.workload, args.prec, args.steps, args.warmup, I, ader, torch, kw2)
+            runs[str(g)] = {
+                "initial_guess": g,
+                "picard_sweeps": sweeps_of(head2["prob"]),
+                "value": head2["value"],
+                "ms_per_step": head2["elapsed"] / args.steps * 1e3,
+                "fp64_value": ref2["value"],
+                "speedup_vs_fp64": head2["value"] / ref2["value"],
+                "speedup_vs_plain_fp64": head2["value"] / ref["value"],
+                "rel_l2_vs_fp64_path": max(l2g),
+                "roofline": roof(head2, args.prec),
+                "state_finite": head2["finite"],
+                "note": "same workload, " + notes[g] + "; error against the FP64 path run with the same guess",
+            }
+            del ref2, head2
+        line["initial_guess_runs"] = runs
     if args.workload == "density" and args.prec != "fp64" and not args.no_exact:
         kwe = dict(nel=args.nel or None, degree=None if args.degree < 0 else args.degree)
         line["exact_solution_error"] = {

@@ -85,14 +85,23 @@ typedef struct {
   const double *material; /* ELASTIC: HOST array [E][3] = (rho, lambda, mu),
                              copied at create; ignored for Euler */
   int32_t prec;         /* ader_prec */
-  int32_t picard_iters; /* Picard sweeps P; 0 -> max(1, N+1-guess) */
+  int32_t picard_iters; /* Picard sweeps P; 0 -> max(1, N+1-guess), 1 for guess 3 */
   double cfl;           /* dt = cfl * alpha_N / max_e sum_d lambda_d / h_d,  0 < cfl <= 1 */
   int32_t guess;        /* initial guess of the Picard iteration (Sec. 2.2), a Taylor
                            polynomial in t - t^n at the time nodes: 0 q0 = u (constant);
                            1 q0 = u + (t-t^n) L(u) (MUSCL-Hancock type, second order);
                            2 q0 = u + (t-t^n) k1 + (t-t^n)^2 (k2-k1)/(2 dt), k1 = L(u),
-                           k2 = L(u + dt k1) (third order); L = S - div F - B.grad.
-                           Guesses 1 and 2 are computed in the sweeps' precision. */
+                           k2 = L(u + dt k1) (third order); L = S - div F - B.grad;
+                           3 extrapolation of the previous interval: the predictor of the
+                           step before (degree N in time), continued to the new time nodes
+                           and shifted to start at the corrected state,
+                           q0 = u + q_prev(t) - q_prev(t^n), with one sweep by default (a
+                           guess of degree >= N-1 in time needs a single sweep).  The context
+                           keeps N Taylor coefficients per node and variable of the last
+                           predictor (8 or 4 bytes each); a step without them (the first, one
+                           on another buffer than the last step wrote, or after a step of
+                           size 0) is the plain scheme: constant guess, N+1 sweeps.
+                           Guesses 1 to 3 are computed in the sweeps' precision. */
   int32_t face_avg;     /* 0: the jump term at every face node and time node, integrated in
                            time (eqs. pc.scheme, rusanov); 1: from time-averaged traces,
                            qbar = sum w_l q(l) and (Euler) Fbar = sum w_l F(q(l)):

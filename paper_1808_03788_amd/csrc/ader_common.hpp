@@ -20,6 +20,8 @@ struct Ops {
   double F0[kMaxN], F1[kMaxN];  // phi_k(0), phi_k(1): face extrapolation
   double L0[kMaxN], L1[kMaxN];  // lifting phi_k(0)/w_k, phi_k(1)/w_k
   double Trow[kMaxN];           // row sums of T (applied to a time-constant right-hand side)
+  double TE[kMaxN * kMaxN];     // TE[p][j]: coefficient of (tau - 1)^p in phi_j(tau) (Taylor
+                                // coefficients about the end of the interval, p = 0..N)
 };
 
 // Host: build the tables of degree N (0..7).  Returns 0 on success.

@@ -191,7 +191,12 @@ struct PredArgs {
                         // double for FP64, float for the mixed modes
   double *acc_glob;     // FP64 accumulator when it does not fit in LDS: [E][M][ACC]
   int sweeps;
-  int guess;            // initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type
+  int guess;            // initial guess: 0 constant, 1 MUSCL-Hancock type, 2 third-order Taylor type,
+                        // 3 extrapolation of the previous interval
+  void *hist;           // guess 3: [E][M][N][ND] Taylor coefficients (orders 1..N) of the last
+                        // interval's predictor about its end; double (FP64) or float (mixed)
+  const double *dtprev; // guess 3: [nprob] step of that interval
+  const int *hist_ok;   // guess 3: the history holds the interval before the state in u
   int face_avg;         // traces as time averages (qbar and, for Euler, Fbar_A) instead of per time node
 };
 
@@ -808,6 +813,66 @@ __device__ __forceinline__ void initial_guess(PArg &P, T *sq, T *sk, const doubl
   __syncthreads();
 }
 
+// Initial guess 3 (Sec. 2.2: extrapolation of q_h from the previous time
+// interval): the previous interval's predictor, continued to the new time
+// nodes and shifted to start at the corrected state,
+//   q0(l, k) = u(k) + sum_{p=1..N} c_p(k) (xi_l r)^p,   r = dt / dt_prev,
+// c_p the Taylor coefficients of that predictor about the end of its
+// interval (written by write_history).  Fills sq in the space-time layout
+// from the u values each thread holds.
+template <int D, int N, class PDE, typename T, int BS, typename TH>
+__device__ __forceinline__ void extrap_guess(PArg &P, T *sq, const double *ureg, const TH *he, T r) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  constexpr int NU = TimeItems<D, N, M, BS>::value;
+#pragma unroll
+  for (int it = 0; it < NU; it++) {
+    const int i = threadIdx.x + it * BS;
+    if (i < M * ND) {
+      const int v = i / ND, k = i - v * ND;
+      T c[N > 0 ? N : 1];
+#pragma unroll
+      for (int p = 0; p < N; p++) c[p] = (T)he[(v * N + p) * ND + k];
+      const T u0 = (T)ureg[it];
+#pragma unroll
+      for (int l = 0; l < n; l++) {
+        const T x = opXi<T>(P, l) * r;
+        T acc = u0, xp = x;
+#pragma unroll
+        for (int p = 0; p < N; p++) {
+          acc += c[p] * xp;
+          xp *= x;
+        }
+        sq[v * NST + l * ND + k] = acc;
+      }
+    }
+  }
+}
+
+// Taylor coefficients (orders 1..N) about the end of the interval of the
+// final predictor qf, stored as TH for the next step's guess 3.
+template <int D, int N, class PDE, typename TH, int BS>
+__device__ __forceinline__ void write_history(PArg &P, const double *qf, int64_t e) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
+  if constexpr (N > 0) {
+    auto *he = as_global((TH *)P.hist + e * (int64_t)(M * N * ND));
+    for (int i = threadIdx.x; i < M * ND; i += BS) {
+      const int v = i / ND, k = i - v * ND;
+      double q[n];
+#pragma unroll
+      for (int j = 0; j < n; j++) q[j] = qf[v * NST + j * ND + k];
+#pragma unroll
+      for (int p = 1; p <= N; p++) {
+        double c = 0.0;
+#pragma unroll
+        for (int j = 0; j < n; j++) c += cload(&P.ops->TE[p * kMaxN + j]) * q[j];
+        he[(v * N + p - 1) * ND + k] = (TH)c;
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- MFMA sweep
 //
 // FP32 Picard sweep whose operator contractions run on v_mfma_f32_4x4x1_16b:
@@ -1308,6 +1373,7 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   if (qo)
     for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
+  if (P.guess == 3) write_history<D, N, PDE, TT, BS>(P, qf, e);
   if (!P.face_avg) {
     traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
     if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
@@ -1401,16 +1467,34 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     const int i = threadIdx.x + r * BS;
     ureg[r] = i < M * ND ? ue[i] : 0.0;
   }
+  // guess and sweep count of this step; guess 3 without a usable previous
+  // interval (the first step, or one after a zero step) is the plain
+  // scheme: constant guess, N+1 sweeps
+  int sweeps = P.sweeps, gm = P.guess;
+  double ratio = 0.0;
+  if (gm == 3) {
+    const double dp = (N > 0 && cload(P.hist_ok) != 0) ? cload(&P.dtprev[P.pidx]) : 0.0;
+    if (dp > 0.0) {
+      ratio = dt / dp;
+    } else {
+      gm = 0;
+      sweeps = N + 1;
+    }
+  }
+  const int64_t hoff = e * (int64_t)(M * (N > 0 ? N : 1) * ND);
   if constexpr (PREC == kFP64 && kBFac == kRowGroups) {
     static_assert(PDE::kElastic && kAccLds && !kMfma, "row groups: FP64 elasticity, accumulator in LDS");
     double *sq = (double *)smem_raw;
     double *sS = (double *)(smem_raw + L::A);
     stage_slice0<D, N, PDE, double, BS>(sq, ureg);
     __syncthreads();
-    int full = P.sweeps;
-    if (P.guess == 0) {
+    int full = sweeps;
+    if (gm == 0) {
       first_sweep<D, N, PDE, double, double, false, BS>(P, sq, sS, sq, ureg, dt, irho, lam, mu);
       full -= 1;
+    } else if (gm == 3) {
+      extrap_guess<D, N, PDE, double, BS, double>(P, sq, ureg, (const double *)P.hist + hoff, ratio);
+      __syncthreads();
     } else {
       initial_guess<D, N, PDE, double, false, BS>(P, sq, sS, ureg, dt, irho, lam, mu);
     }
@@ -1423,11 +1507,14 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     // reads only its time slice 0
     stage_slice0<D, N, PDE, double, BS>(sq, ureg);
     __syncthreads();
-    int full = P.sweeps;  // sweeps over all time slices
-    if (P.guess == 0) {
+    int full = sweeps;  // sweeps over all time slices
+    if (gm == 0) {
       // the first sweep starts from the time-constant iterate q^0 = u
       first_sweep<D, N, PDE, double, double, false, BS, kSplit>(P, sq, sacc, sq, ureg, dt, irho, lam, mu);
       full -= 1;
+    } else if (gm == 3) {
+      extrap_guess<D, N, PDE, double, BS, double>(P, sq, ureg, (const double *)P.hist + hoff, ratio);
+      __syncthreads();
     } else {
       initial_guess<D, N, PDE, double, false, BS, kSplit>(P, sq, sacc, ureg, dt, irho, lam, mu);
     }
@@ -1442,7 +1529,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     float *sq32 = (float *)smem_raw;
     double *sR = (double *)(smem_raw + L::A);
     float *sacc32 = (float *)sR;
-    if (P.sweeps == 1 && P.guess == 0) {
+    if (sweeps == 1 && gm == 0) {
       // a single sweep is the FP64 one, from q^0 = u itself: region A holds
       // u (compact), region R the per-axis parts and then the iterate
       static_assert(D * M * ND * 8 <= L::R, "region R holds the per-axis parts");
@@ -1458,12 +1545,16 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     __syncthreads();
     const float dtf = (float)dt;
     // FP32 sweeps over all time slices before the FP64 one
-    int full32 = P.sweeps - 1;
-    if (P.guess == 0) {
+    int full32 = sweeps - 1;
+    if (gm == 0) {
       // first sweep from the time-constant iterate q^0 = u
       first_sweep<D, N, PDE, float, float, kBF, BS, kSplit>(P, sq32, sacc32, sq32, ureg, dtf, (float)irho, (float)lam,
                                                     (float)mu);
       full32 -= 1;
+    } else if (gm == 3) {
+      // with one sweep (the default) it is the FP64 one, from this guess
+      extrap_guess<D, N, PDE, float, BS, float>(P, sq32, ureg, (const float *)P.hist + hoff, (float)ratio);
+      __syncthreads();
     } else {
       initial_guess<D, N, PDE, float, kBF, BS, kSplit>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam,
                                                      (float)mu);
@@ -1500,12 +1591,6 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
   }
 }
 
-// Batched predictor: workgroup b owns tile b, one element of one problem of
-// the batch (one launch per kernel class; the grid is the total tile count).
-// A grid-stride loop over tiles would let the compiler keep every per-thread
-// index of the element phases live across iterations and cost occupancy, so
-// each workgroup takes a single element.  u, dt and the optional q-hat output
-// are the call's buffers (per-problem offsets in the record).
 // Dynamic LDS bytes of a predictor variant: the slot tables, region A and
 // region R (or G for the FP64 row-group sweeps; only A when the FP64
 // accumulator lives in HBM).
@@ -1528,6 +1613,12 @@ __host__ __device__ constexpr int pred_waves_per_eu() {
   return w < 1 ? 1 : (w > 4 ? 4 : w);  // at most 4: small elements keep 128 registers
 }
 
+// Batched predictor: workgroup b owns tile b, one element of one problem of
+// the batch (one launch per kernel class; the grid is the total tile count).
+// A grid-stride loop over tiles would let the compiler keep every per-thread
+// index of the element phases live across iterations and cost occupancy, so
+// each workgroup takes a single element.  u, dt and the optional q-hat output
+// are the call's buffers (per-problem offsets in the record).
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
 __global__ void __launch_bounds__(pred_block(D, N, kBFac))
     __attribute__((amdgpu_waves_per_eu(pred_waves_per_eu<D, N, PDE::M, PREC, kAccLds, kBFac>())))

@@ -42,6 +42,7 @@ struct ProbState {
   Ops *ops_dev = nullptr;   // device copy of the tables (outputs, faces, update read them by pointer)
   double *mat = nullptr, *ustar = nullptr, *acc = nullptr;
   double *summ = nullptr;           // detection: [E][m][2] extremes of the state before a step
+  void *hist = nullptr;             // guess 3: [E][m][N][nd] Taylor coefficients of the last predictor
   int64_t e_off = 0;                // offset of the problem's elements in the flag array
   void *trace[3][2] = {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}};
   void *GL[3] = {nullptr, nullptr, nullptr}, *GR[3] = {nullptr, nullptr, nullptr};  // trace type
@@ -93,6 +94,9 @@ struct ader_ctx {
   unsigned long long *smax = nullptr;                      // device [nprob], time-step kernel maxima
   unsigned long long *smax_f = nullptr;                    // device [nprob], maxima taken by the update
   const double *fused_u = nullptr;  // state buffer whose maxima smax_f holds (written by the last step)
+  int *hist_ok = nullptr;           // device [1]: the guess-3 history belongs to the state in hist_u
+  double *dtprev = nullptr;         // device [nprob]: step of the last completed step
+  const double *hist_u = nullptr;   // state buffer of the last completed ader_step / ader_run
   int *err = nullptr;                                      // device [1]
   double *partial = nullptr, *sums = nullptr;              // totals scratch
   int64_t total_u = 0, total_q = 0, total_m = 0;
@@ -162,7 +166,7 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
   if (d.prec != ADER_FP64 && d.prec != ADER_FP32 && d.prec != ADER_BF16)
     return fail(c, ADER_ERR_INVALID, w + "unknown precision");
   if (d.picard_iters < 0) return fail(c, ADER_ERR_INVALID, w + "picard_iters must be >= 0");
-  if (d.guess < 0 || d.guess > 2) return fail(c, ADER_ERR_INVALID, w + "guess must be 0, 1 or 2");
+  if (d.guess < 0 || d.guess > 3) return fail(c, ADER_ERR_INVALID, w + "guess must be 0, 1, 2 or 3");
   if (d.face_avg != 0 && d.face_avg != 1) return fail(c, ADER_ERR_INVALID, w + "face_avg must be 0 or 1");
   if (!(d.cfl > 0.0) || d.cfl > 1.0) return fail(c, ADER_ERR_INVALID, w + "cfl must be in (0, 1]");
   return ADER_OK;
@@ -211,10 +215,18 @@ __global__ void k_zero_u64(unsigned long long *p, int n) {
   if (i < n) p[i] = 0ull;
 }
 
-__global__ void k_commit(double *t, const double *tnext, int np) {
+// End of a step: the new time, the step just taken (the previous interval
+// of the next step's guess 3) and the mark that the history is current.
+__global__ void k_commit(double *t, const double *tnext, const double *dt, double *dtprev, int *hist_ok, int np) {
   const int i = threadIdx.x + blockIdx.x * blockDim.x;
-  if (i < np) t[i] = tnext[i];
+  if (i < np) {
+    t[i] = tnext[i];
+    dtprev[i] = dt[i];
+  }
+  if (i == 0) *hist_ok = 1;
 }
+
+__global__ void k_set_int(int *p, int v) { *p = v; }
 
 // Conservation sums: per-block partial sums in a fixed order, then a
 // sequential pass over the blocks; deterministic for a given grid.
@@ -308,8 +320,11 @@ __global__ void k_fill_state(double *u, int64_t count, int m, int nd, double v0,
 std::mutex g_tune_mu;
 std::map<std::string, std::string> g_tune_cache;  // configuration -> variant name
 
-PredArgs pred_args(const ProbState &s, int p) {
+PredArgs pred_args(const ader_ctx *c, const ProbState &s, int p) {
   PredArgs a{};
+  a.hist = s.hist;
+  a.dtprev = c->dtprev;
+  a.hist_ok = c->hist_ok;
   a.sw = s.sw_dev;
   a.ops = s.ops_dev;
   a.g = s.g;
@@ -375,7 +390,7 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
     return ADER_OK;  // no room to tune: keep the default
   }
   double *ut = sc.ut;
-  PredArgs a = pred_args(s, pl);
+  PredArgs a = pred_args(c, s, pl);
   a.u_off = 0;
   const int64_t start[2] = {0, Et};
   PredArgs *a_dev = nullptr;
@@ -393,6 +408,11 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
                        1.0, 1.0);
   const double dt_tune = 1e-6;
   HIP_OR_FAIL(c, hipMemcpyAsync(c->dt + pl, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->cur));
+  if (s.desc.guess == 3) {  // time the steady state: a previous interval (zero history) of the same step
+    const int one = 1;
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->dtprev + pl, &dt_tune, sizeof(double), hipMemcpyHostToDevice, c->cur));
+    HIP_OR_FAIL(c, hipMemcpyAsync(c->hist_ok, &one, sizeof(int), hipMemcpyHostToDevice, c->cur));
+  }
   HIP_OR_FAIL(c, hipEventCreate(&sc.e0));
   HIP_OR_FAIL(c, hipEventCreate(&sc.e1));
   hipEvent_t e0 = sc.e0, e1 = sc.e1;
@@ -424,7 +444,10 @@ ader_status tune_class(ader_ctx *c, KClass &k, const std::vector<PredVariant> &c
   HIP_OR_FAIL(c, hipStreamSynchronize(c->cur));
   if (st) return st;
   const double zero = 0.0;
+  const int izero = 0;
   HIP_OR_FAIL(c, hipMemcpy(c->dt + pl, &zero, sizeof(double), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->dtprev + pl, &zero, sizeof(double), hipMemcpyHostToDevice));
+  HIP_OR_FAIL(c, hipMemcpy(c->hist_ok, &izero, sizeof(int), hipMemcpyHostToDevice));
   k.pv = bestv;
   k.tuned = true;
   k.tune_ms = best;
@@ -450,7 +473,7 @@ ader_status build_class(ader_ctx *c, KClass &k) {
     s.pv = k.pv;
     s.tuned = k.tuned;
     s.tune_ms = k.tune_ms;
-    pa[i] = pred_args(s, p);
+    pa[i] = pred_args(c, s, p);
     const int nx = s.g.nel[0], rows = s.g.nel[1] * s.g.nel[2];
     for (int ax = 0; ax < s.D; ax++) {
       FaceArgs &f = fa[ax][i];
@@ -660,6 +683,17 @@ ader_status set_tend(ader_ctx *c, const double *t_end_host) {
   return ADER_OK;
 }
 
+// The guess-3 history (the previous interval's predictor) is current only
+// for the state the last step of this context wrote: before a step on any
+// other buffer, mark it stale (that step is then the plain scheme).
+ader_status history_for(ader_ctx *c, const double *u) {
+  if (c->hist_u == u) return ADER_OK;
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(1), 0, c->stream, c->hist_ok, 0);
+  HIP_OR_FAIL(c, hipGetLastError());
+  c->hist_u = nullptr;
+  return ADER_OK;
+}
+
 // The launches of one step on c->cur: dt, predictor, faces, update, commit
 // of the new time.  Profiling events are recorded only outside captures.
 // With `fused` the step's dt comes from the maxima the previous step's
@@ -677,7 +711,8 @@ ader_status step_launches(ader_ctx *c, double *u, bool marks, bool fused) {
   if (c->detect && (st = run_detect(c, u))) return st;  // timed with the update stage
   if (m && (st = mark(c))) return st;
   const int np = (int)c->P.size();
-  hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->t, c->tnext, np);
+  hipLaunchKernelGGL(k_commit, dim3((np + 255) / 256), dim3(256), 0, c->cur, c->t, c->tnext, c->dt, c->dtprev,
+                     c->hist_ok, np);
   HIP_OR_FAIL(c, hipGetLastError());
   return ADER_OK;
 }
@@ -767,7 +802,9 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       return bail(ADER_ERR_INVALID);
     }
     s.coef = d.cfl * stability_alpha(s.N);
-    s.sweeps = d.picard_iters > 0 ? d.picard_iters : (s.N + 1 - d.guess > 1 ? s.N + 1 - d.guess : 1);
+    s.sweeps = d.picard_iters > 0 ? d.picard_iters
+               : d.guess == 3      ? 1
+                                   : (s.N + 1 - d.guess > 1 ? s.N + 1 - d.guess : 1);
     s.u_off = uoff;
     s.u_cnt = s.E * s.m * s.nd;
     s.q_off = qoff;
@@ -844,6 +881,14 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       if ((st = dalloc(c, (void **)&s.GL[a], gb))) return bail(st);
       if (d.pde == ADER_ELASTIC && (st = dalloc(c, (void **)&s.GR[a], gb))) return bail(st);
     }
+    if (d.guess == 3 && s.N > 0) {  // previous interval: N Taylor coefficients per node and variable
+      const size_t hb = (size_t)s.E * s.m * s.N * s.nd * s.trace_elt;
+      if ((st = dalloc(c, &s.hist, hb))) return bail(st);
+      if (hipMemset(s.hist, 0, hb) != hipSuccess) {
+        c->msg = "history initialisation failed";
+        return bail(ADER_ERR_DEVICE);
+      }
+    }
     // every candidate shares acc_lds (the first pass that finds any fixes it)
     if (!s.pv.acc_lds && (st = dalloc(c, (void **)&s.acc, (size_t)s.E * acc_bytes))) return bail(st);
     if (d.pde == ADER_ELASTIC) {
@@ -863,6 +908,8 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   if ((st = dalloc(c, (void **)&c->tnext, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->smax, nprob * sizeof(unsigned long long)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->smax_f, nprob * sizeof(unsigned long long)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->dtprev, nprob * sizeof(double)))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->hist_ok, sizeof(int)))) return bail(st);
   {
     std::vector<double> coef(nprob);
     for (int i = 0; i < nprob; i++) coef[i] = c->P[i].coef;
@@ -879,6 +926,8 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
       hipMemset(c->tnext, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->smax, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
       hipMemset(c->smax_f, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->dtprev, 0, nprob * sizeof(double)) != hipSuccess ||
+      hipMemset(c->hist_ok, 0, sizeof(int)) != hipSuccess ||
       hipMemset(c->err, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
     c->msg = "initialisation failed";
     return bail(ADER_ERR_DEVICE);
@@ -1004,6 +1053,7 @@ ader_status ader_predictor(ader_ctx *c, const double *u, const double *dt_dev, d
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
   c->fused_u = nullptr;
+  c->hist_u = nullptr;
   return run_predictor(c, u, dt_dev, qhat_out);
 }
 
@@ -1011,6 +1061,7 @@ ader_status ader_corrector(ader_ctx *c, double *u, const double *dt_dev) {
   if (!c) return ADER_ERR_INVALID;
   if (!u) return fail(c, ADER_ERR_INVALID, "u is NULL");
   c->fused_u = nullptr;
+  c->hist_u = nullptr;
   return run_corrector(c, u, dt_dev);
 }
 
@@ -1021,8 +1072,10 @@ ader_status ader_step(ader_ctx *c, double *u, const double *t_end_host) {
   if (st) return st;
   const bool fused = !c->detect && c->fused_u == u;
   c->fused_u = nullptr;
+  if ((st = history_for(c, u))) return st;
   if ((st = step_launches(c, u, true, fused))) return st;
   c->fused_u = c->detect ? nullptr : u;
+  c->hist_u = u;
   return ADER_OK;
 }
 
@@ -1074,6 +1127,7 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
     HIP_OR_FAIL(c, hipGetLastError());
     if ((st = run_maxima(c, u, c->smax_f))) return st;
   }
+  if ((st = history_for(c, u))) return st;
   // order the replay after earlier work on the context stream, and later work after it
   HIP_OR_FAIL(c, hipEventRecord(c->g_in, c->stream));
   HIP_OR_FAIL(c, hipStreamWaitEvent(c->gstream, c->g_in, 0));
@@ -1081,6 +1135,7 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
   HIP_OR_FAIL(c, hipEventRecord(c->g_out, c->gstream));
   HIP_OR_FAIL(c, hipStreamWaitEvent(c->stream, c->g_out, 0));
   c->fused_u = c->detect ? nullptr : u;
+  c->hist_u = u;
   return ADER_OK;
 }
 

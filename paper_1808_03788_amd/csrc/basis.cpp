@@ -166,6 +166,21 @@ int build_ops(int N, Ops *o) {
       o->T[a * kMaxN + b] = W[a * n + b];
       o->V[a * kMaxN + b] = o->w[b] * Dn[b * n + a] / o->w[a];
     }
+  // Taylor coefficients of the basis about tau = 1: with V[l][p] = (xi_l - 1)^p,
+  // phi_j(tau) = sum_p (V^{-1})[p][j] (tau - 1)^p
+  {
+    double V[kMaxN * kMaxN], Id[kMaxN * kMaxN];
+    for (int l = 0; l < n; l++)
+      for (int q = 0; q < n; q++) {
+        double pw = 1.0;
+        for (int r = 0; r < q; r++) pw *= (x[l] - 1.0);
+        V[l * n + q] = pw;
+        Id[l * n + q] = (l == q) ? 1.0 : 0.0;
+      }
+    if (lu_solve(n, V, Id)) return -3;
+    for (int q = 0; q < n; q++)
+      for (int j = 0; j < n; j++) o->TE[q * kMaxN + j] = Id[q * n + j];
+  }
   for (int k = 0; k < n; k++) {
     o->L0[k] = o->F0[k] / o->w[k];
     o->L1[k] = o->F1[k] / o->w[k];

@@ -83,7 +83,7 @@ def _bad(**kw):
     (dict(cfl=0.0), A.ADER_ERR_INVALID),
     (dict(cfl=1.5), A.ADER_ERR_INVALID),
     (dict(picard=-2), A.ADER_ERR_INVALID),
-    (dict(guess=3), A.ADER_ERR_INVALID),
+    (dict(guess=4), A.ADER_ERR_INVALID),
     (dict(guess=-1), A.ADER_ERR_INVALID),
 ])
 def test_create_rejects_bad_arguments(kw, status):

@@ -472,6 +472,66 @@ def test_initial_guesses(A, orc, name, mk, init, steps, prec, guess):
     check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec} guess={guess}")
 
 
+def orc_run_hist(orc, prob, u0, steps, t_end=1e9):
+    """Oracle steps that carry the previous interval (guess 3)."""
+    u, t, hist = u0, 0.0, None
+    for _ in range(steps):
+        u, t, _, hist = orc.step_hist(prob, u, t, t_end, hist)
+    return u, t
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,mk,init,steps", GUESS_CASES, ids=[c[0] for c in GUESS_CASES])
+def test_extrapolation_guess(A, orc, name, mk, init, steps, prec):
+    """Guess 3 (the previous interval's predictor continued in time) with
+    its default single sweep: the first step is the plain scheme, every
+    later one starts from the history the step before wrote."""
+    prob = mk(prec, 3)
+    u0 = init(prob)
+    say(f"[guess] {name} {prec} guess=3")
+    ug, tg = gpu_run(A, prob, u0, steps)
+    uo, to = orc_run_hist(orc, mk("fp64", 3), u0, steps)
+    # the mixed path's states differ at the FP32 level, and so do its CFL steps
+    assert abs(tg - to) <= (1e-14 if prec == "fp64" else 1e-6) * max(1.0, abs(to))
+    check(prob, ug, uo, tol=TOL64 if prec == "fp64" else 1e-6, what=f"{name} {prec} guess=3")
+
+
+def test_extrapolation_guess_history_follows_the_state(A, orc):
+    """The history belongs to the buffer the last step wrote: graph replays
+    carry it across steps and replays (bit for bit equal to single steps),
+    and a step on another buffer is the plain scheme again."""
+    import torch
+    prob = I.Problem(dim=3, N=3, nel=(3, 2, 4), lo=(0, 0, 0), hi=(1, 1, 1), guess=3)
+    u0 = I.density_wave(prob)
+    ctx = A.Context([prob])
+    try:
+        u = ctx.upload([u0])
+        for _ in range(5):
+            ctx.step(u, 1e9)
+        torch.cuda.synchronize()
+        steps5 = ctx.download(u)[0]
+    finally:
+        ctx.close()
+    ctx = A.Context([prob])
+    try:
+        u = ctx.upload([u0])
+        ctx.run(u, [1e9], 2)
+        ctx.run(u, [1e9], 3)
+        torch.cuda.synchronize()
+        graph5 = ctx.download(u)[0]
+        # a copy of the state in a new buffer: its first step has no history
+        u2 = ctx.upload([graph5])
+        ctx.set_time([0.0])
+        ctx.step(u2, 1e9)
+        torch.cuda.synchronize()
+        fresh = ctx.download(u2)[0]
+    finally:
+        ctx.close()
+    assert np.array_equal(steps5.view(np.uint64), graph5.view(np.uint64))
+    uo, _, _, _ = orc.step_hist(prob, graph5, 0.0, 1e9, None)
+    check(prob, fresh, uo, what="fresh buffer, no history")
+
+
 AVG_CASES = [
     ("euler3d_N4", lambda pr: I.Problem(dim=3, N=4, nel=(3, 4, 2), lo=(0, 0, 0), hi=(1, 1, 1), prec=pr, face_avg=1),
      lambda p: I.density_wave(p), 4),
