@@ -256,9 +256,15 @@ constexpr int kSplitLines = 4;
 // groups of a sweep one after the other (elastic_group_sweep).
 constexpr int kRowGroups = 8;
 __host__ __device__ constexpr int round64(int x) { return (x + 63) / 64 * 64; }
+// Factor kWide (elements with more than 128 lines per axis phase, whose LDS
+// footprint leaves one or two workgroups per CU): 512 threads (1024 above
+// 256 lines), four wavefronts per SIMD instead of two, and room to pair
+// two axis phases.
+constexpr int kWide = 16;
 __host__ __device__ constexpr int pred_block_cap(int D, int N) { return ipow(N + 1, D) > 256 ? 512 : 256; }
 __host__ __device__ constexpr int pred_block(int D, int N, int factor = 1) {
-  return factor == kRowGroups ? pred_block(D, N, 1)
+  return factor == kWide ? (ipow(N + 1, D) > 256 ? 1024 : (ipow(N + 1, D) > 128 ? 512 : pred_block(D, N, 2)))
+         : factor == kRowGroups ? pred_block(D, N, 1)
          : factor == kSplitLines
              ? 2 * round64(ipow(N + 1, D))
              : ((ipow(N + 1, D) <= 64 ? 64 : (ipow(N + 1, D) <= 128 ? 128 : 256)) * factor > pred_block_cap(D, N)
@@ -1518,8 +1524,9 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     } else {
       initial_guess<D, N, PDE, double, false, BS, kSplit>(P, sq, sacc, ureg, dt, irho, lam, mu);
     }
-    // no room for a second FP64 accumulator: paired axes hold axis 1 in registers
-    constexpr int kPair64 = (!kSplit && pair_axes<D, N, BS>()) ? kPairHeld : 0;
+    // no room for a second FP64 accumulator: paired axes hold axis 1 in
+    // registers (not in 1024-thread blocks, which have 128 registers)
+    constexpr int kPair64 = (!kSplit && kBFac != kWide && pair_axes<D, N, BS>()) ? kPairHeld : 0;
     for (int s = 0; s < full; s++)
       picard_sweep<D, N, PDE, double, double, double, false, BS, kSplit, kPair64>(P, sq, sacc, sq, ureg, dt, irho,
                                                                                  lam, mu);
@@ -1584,7 +1591,8 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
     // paired with axis 1 held in registers where an axis phase spans more
     // than one wavefront (at N = 3 in 3-D the extra registers cost this
     // kernel a wavefront of occupancy and the sweep was slower)
-    constexpr int kPairR = (!kSplit && pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairHeld : 0;
+    constexpr int kPairR =
+        (!kSplit && kBFac != kWide && pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairHeld : 0;
     picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit, kPairR>(P, sq32, sR, sR, ureg, dt, irho, lam,
                                                                              mu);
     predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);

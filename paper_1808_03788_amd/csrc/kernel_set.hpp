@@ -15,7 +15,7 @@ struct PredVariant {
   const char *name = "";
 };
 
-constexpr int kMaxVariants = 16;
+constexpr int kMaxVariants = 24;
 
 struct KernelSet {
   PredVariant pred[kMaxVariants];
@@ -57,6 +57,13 @@ KernelSet make_kernel_set() {
   add_variant<D, N, PDE, kFP32, true, true, 2>(k, "fp32-mfma-b2");
   add_variant<D, N, PDE, kBF16, true, false, 1>(k, "bf16-valu-b1");
   add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
+  if constexpr (ipow(N + 1, D) > 128) {
+    // one or two workgroups per CU: also 512- or 1024-thread blocks (the
+    // FP64 and MFMA line phases of these elements do not fit the 128
+    // registers they allow)
+    add_variant<D, N, PDE, kFP32, true, false, kWide>(k, "fp32-valu-w4");
+    add_variant<D, N, PDE, kBF16, true, false, kWide>(k, "bf16-valu-w4");
+  }
   if constexpr (PDE::kElastic && D == 3) {
     add_variant<D, N, PDE, kFP64, true, false, kSplitLines>(k, "fp64-valu-split");
     add_variant<D, N, PDE, kFP64, false, false, kSplitLines>(k, "fp64-valu-hbmacc-split");
