@@ -8,7 +8,13 @@ namespace ader {
 constexpr int kMaxN = 8;      // largest n = N+1
 constexpr int kBlock = 256;   // threads per workgroup of the element kernels
 
-__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+// Iterative, so that it always inlines: the recursive form was left as a
+// device call in some kernels, with a dynamic stack and spills.
+__host__ __device__ __forceinline__ constexpr int ipow(int b, int e) {
+  int r = 1;
+  for (int i = 0; i < e; i++) r *= b;
+  return r;
+}
 
 // 1-D tables of one degree, FP64 (Sec. 2.1: nodal Lagrange basis on the
 // Gauss-Legendre points of [0,1]).  Row stride kMaxN.
