@@ -497,7 +497,7 @@ ader_status build_class(ader_ctx *c, KClass &k) {
     }
     u.u_off = s.u_off;
     u.pidx = p;
-    const int ept = upd_elems(s.D, s.N);
+    const int ept = upd_elems(s.D, s.N, s.m);
     u.cx = (nx + ept - 1) / ept;
     for (int ax = 0; ax < 3; ax++) u.h[ax] = s.h[ax];
     u.mat = s.mat;
