@@ -64,8 +64,12 @@ typedef enum { ADER_EULER = 0, ADER_ELASTIC = 1 } ader_pde;
  * cores (v_mfma_f32_4x4x1, rows in groups of four, the rest on VALU) or as
  * VALU FMAs, whichever the timing at ader_create finds faster for the
  * configuration (ader_describe names the variant in use: fp32-mfma-* or
- * fp32-valu-*).  ADER_BF16: like FP32 but the contraction inputs are
- * rounded to bfloat16.  The corrector's update u^{n+1} = u^n + dt*R, the
+ * fp32-valu-*).  ADER_BF16: like FP32 but the inputs of the spatial
+ * contractions (flux, or q for elasticity) are rounded to bfloat16; they run
+ * as VALU FMAs with the FP32 operator (bf16-valu-*) or on the matrix cores
+ * (bf16-mfma-*: v_mfma_f32_4x4x4bf16_1k, the operator split into two
+ * bfloat16 parts), again chosen by timing; FP32 accumulation and FP32 time
+ * contraction.  The corrector's update u^{n+1} = u^n + dt*R, the
  * time-step reduction and the conservation sums are FP64 in every mode. */
 typedef enum { ADER_FP64 = 0, ADER_FP32 = 1, ADER_BF16 = 2 } ader_prec;
 

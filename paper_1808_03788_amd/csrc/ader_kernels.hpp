@@ -899,6 +899,18 @@ __device__ __forceinline__ void write_history(PArg &P, const double *qf, int64_t
 // needed.
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef short s4v __attribute__((ext_vector_type(4)));  // four bfloat16 values
+
+// BF16 variant of the spatial contractions: v_mfma_f32_4x4x4bf16_1k takes
+// four bfloat16 values of K per lane, A[i][kk] from lane 4b+i and B[kk][j]
+// from lane 4b+j, so a lane supplies four consecutive nodes of its own line
+// as B and the operator row chunk as A; n nodes take ceil(n/4) instructions
+// per row group.  The contraction inputs (flux, or q for elasticity) are
+// rounded to bfloat16 as in the BF16 VALU sweeps; the operator is split into
+// a bfloat16 high part and a bfloat16 remainder (two instructions per chunk,
+// operator accurate to about 2^-16 instead of 2^-8); FP32 accumulation.  The
+// time contraction stays on the FP32 MFMA path.
+__device__ __forceinline__ short bf16_bits(float x) { return (short)(__float_as_uint(round_bf16(x)) >> 16); }
 
 // Row groups of four on MFMA, and rows left to VALU, for n nodes.
 __host__ __device__ constexpr int mfma_groups(int n) { return (n == 5 || n == 6) ? 1 : (n + 3) / 4; }
@@ -913,31 +925,44 @@ __host__ __device__ constexpr int mfma_valu_rows(int n) { return n - 4 * mfma_gr
 // through the coefficients of B_A.
 template <int N>
 struct MfmaOps {
-  static constexpr int n = N + 1, G = mfma_groups(N + 1);
+  static constexpr int n = N + 1, G = mfma_groups(N + 1), JC = (N + 4) / 4;
   float D[G][n];
   float T[G][n];
+  s4v Dh[G][JC], Dl[G][JC];  // BF16 variant: high part and remainder, nodes 4jc .. 4jc+3
 };
 
-template <int N, class PDE>
+template <int N, class PDE, bool kBF = false>
 __device__ __forceinline__ void load_mfma_ops(PArg &P, float dt, MfmaOps<N> &o) {
-  constexpr int n = N + 1, G = mfma_groups(n);
+  constexpr int n = N + 1, G = mfma_groups(n), JC = MfmaOps<N>::JC;
   const int lane = threadIdx.x & 63;
   const float sT = PDE::kElastic ? dt : -dt * (float)P.g.inv_h[0];
 #pragma unroll
-  for (int c = 0; c < G; c++)
+  for (int c = 0; c < G; c++) {
+    const int k = 4 * c + (lane & 3);
 #pragma unroll
     for (int j = 0; j < n; j++) {
-      const int k = 4 * c + (lane & 3);
       o.D[c][j] = k < n ? P.sw->Dhf[k * kMaxN + j] : 0.f;
       o.T[c][j] = k < n ? sT * P.sw->Tf[k * kMaxN + j] : 0.f;
     }
+    if constexpr (kBF)
+#pragma unroll
+      for (int jc = 0; jc < JC; jc++)
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) {
+          const int j = 4 * jc + kk;
+          const float d = (k < n && j < n) ? P.sw->Dhf[k * kMaxN + j] : 0.f;
+          const float hi = round_bf16(d);
+          o.Dh[c][jc][kk] = bf16_bits(hi);
+          o.Dl[c][jc][kk] = bf16_bits(d - hi);
+        }
+  }
 }
 
 // Right-hand side along axis A for the lines L0 + lane of one wavefront
 // (all lanes take part in the MFMAs; lanes past the last line compute on
 // the line L0 and store nothing), written to sacc (kAcc: added to it), in
 // the scaling of MfmaOps.
-template <int D, int N, class PDE, int A, bool kAcc>
+template <int D, int N, class PDE, int A, bool kAcc, bool kBF = false>
 __device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const float *sq, float *sacc, int L0,
                                            float irho, float lam, float mu) {
   using S = Shape<D, N>;
@@ -984,15 +1009,43 @@ __device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const f
     for (int r = 0; r < VR; r++)
       accv[r][v] = (!PDE::kElastic && kAcc && own) ? sacc[v * NST + base + (4 * G + r) * ST] : 0.f;
   }
+  if constexpr (kBF) {
+    constexpr int JC = MfmaOps<N>::JC;
 #pragma unroll
-  for (int j = 0; j < n; j++)
+    for (int j = 0; j < n; j++)
 #pragma unroll
-    for (int v = 0; v < M; v++) {
+      for (int v = 0; v < M; v++) X[j][v] = round_bf16(X[j][v]);
 #pragma unroll
-      for (int c = 0; c < G; c++) acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.D[c][j], X[j][v], acc[c][v], 0, 0, 0);
+    for (int v = 0; v < M; v++)
 #pragma unroll
-      for (int r = 0; r < VR; r++) accv[r][v] += cload(&P.sw->Dhf[(4 * G + r) * kMaxN + j]) * X[j][v];
-    }
+      for (int jc = 0; jc < JC; jc++) {
+        s4v xb;
+#pragma unroll
+        for (int kk = 0; kk < 4; kk++) xb[kk] = 4 * jc + kk < n ? bf16_bits(X[4 * jc + kk < n ? 4 * jc + kk : 0][v]) : 0;
+#pragma unroll
+        for (int c = 0; c < G; c++) {
+          acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(o.Dh[c][jc], xb, acc[c][v], 0, 0, 0);
+          acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x4bf16_1k(o.Dl[c][jc], xb, acc[c][v], 0, 0, 0);
+        }
+      }
+#pragma unroll
+    for (int j = 0; j < n; j++)
+#pragma unroll
+      for (int v = 0; v < M; v++)
+#pragma unroll
+        for (int r = 0; r < VR; r++) accv[r][v] += cload(&P.sw->Dhf[(4 * G + r) * kMaxN + j]) * X[j][v];
+  } else {
+#pragma unroll
+    for (int j = 0; j < n; j++)
+#pragma unroll
+      for (int v = 0; v < M; v++) {
+#pragma unroll
+        for (int c = 0; c < G; c++)
+          acc[c][v] = __builtin_amdgcn_mfma_f32_4x4x1f32(o.D[c][j], X[j][v], acc[c][v], 0, 0, 0);
+#pragma unroll
+        for (int r = 0; r < VR; r++) accv[r][v] += cload(&P.sw->Dhf[(4 * G + r) * kMaxN + j]) * X[j][v];
+      }
+  }
   if (!own) return;
   // elasticity: B_A with -1/h_A folded into its coefficients
   const float sh = PDE::kElastic ? -(float)P.g.inv_h[A] : 1.f;
@@ -1017,13 +1070,13 @@ __device__ __forceinline__ void mfma_lines(PArg &P, const MfmaOps<N> &o, const f
   }
 }
 
-template <int D, int N, class PDE, int A, bool kAcc, int WAVES, int W0 = 0>
+template <int D, int N, class PDE, int A, bool kAcc, int WAVES, int W0 = 0, bool kBF = false>
 __device__ __forceinline__ void mfma_axis(PArg &P, const MfmaOps<N> &o, const float *sq, float *sacc, float irho,
                                           float lam, float mu) {
   constexpr int NS = line_slots_count<D, N>();
   const int wave = (threadIdx.x >> 6) - W0;
   for (int L0 = wave * 64; L0 < NS; L0 += WAVES * 64)
-    mfma_lines<D, N, PDE, A, kAcc>(P, o, sq, sacc, L0, irho, lam, mu);
+    mfma_lines<D, N, PDE, A, kAcc, kBF>(P, o, sq, sacc, L0, irho, lam, mu);
 }
 
 // Time contraction on MFMA: the lane owns the time line (v, k), thread
@@ -1077,7 +1130,7 @@ __device__ __forceinline__ void mfma_time(PArg &P, const MfmaOps<N> &o, const fl
 // of axes pair_a and pair_b run at the same time on the two halves of the
 // block into two accumulators (as rhs_pair); third_axis then accumulates
 // onto the first.
-template <int D, int N, class PDE, int BS>
+template <int D, int N, class PDE, int BS, bool kBF = false>
 __device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, float *sq, float *sacc, float *sacc2,
                                                   const double *ureg, float dt, float irho, float lam, float mu) {
   constexpr int NW = BS / 64;
@@ -1085,23 +1138,23 @@ __device__ __forceinline__ void picard_sweep_mfma(PArg &P, const MfmaOps<N> &o, 
   if constexpr (kPair) {
     constexpr int HW = round64(ipow(N + 1, D)) / 64;  // wavefronts per half
     if ((int)(threadIdx.x >> 6) < HW)
-      mfma_axis<D, N, PDE, pair_a<D, N>(), false, HW, 0>(P, o, sq, sacc, irho, lam, mu);
+      mfma_axis<D, N, PDE, pair_a<D, N>(), false, HW, 0, kBF>(P, o, sq, sacc, irho, lam, mu);
     else if ((int)(threadIdx.x >> 6) < 2 * HW)
-      mfma_axis<D, N, PDE, pair_b<D, N>(), false, HW, HW>(P, o, sq, sacc2, irho, lam, mu);
+      mfma_axis<D, N, PDE, pair_b<D, N>(), false, HW, HW, kBF>(P, o, sq, sacc2, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 2) {
-      mfma_axis<D, N, PDE, third_axis(D, N), true, NW>(P, o, sq, sacc, irho, lam, mu);
+      mfma_axis<D, N, PDE, third_axis(D, N), true, NW, 0, kBF>(P, o, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
   } else {
-    mfma_axis<D, N, PDE, 0, false, NW>(P, o, sq, sacc, irho, lam, mu);
+    mfma_axis<D, N, PDE, 0, false, NW, 0, kBF>(P, o, sq, sacc, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 1) {
-      mfma_axis<D, N, PDE, 1, true, NW>(P, o, sq, sacc, irho, lam, mu);
+      mfma_axis<D, N, PDE, 1, true, NW, 0, kBF>(P, o, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
     if constexpr (D > 2) {
-      mfma_axis<D, N, PDE, 2, true, NW>(P, o, sq, sacc, irho, lam, mu);
+      mfma_axis<D, N, PDE, 2, true, NW, 0, kBF>(P, o, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
   }
@@ -1448,7 +1501,7 @@ __device__ __forceinline__ void stage_slice0(TQ *sq, const double *ureg) {
 //  PREC == kFP32/kBF16: sweeps 1..P-1 in FP32 on an FP32 copy of q (region
 //    A), the last sweep in FP64 from that copy; its iterate lands in region
 //    R and feeds the FP64 outputs; traces are stored in FP32.
-//  kMfma: the FP32 sweeps contract on MFMA instead of VALU FMAs.
+//  kMfma: the FP32 (or BF16-input) sweeps contract on MFMA instead of VALU FMAs.
 //  kBFac: block-size factor (threads = pred_block(D, N, kBFac)); kSplitLines
 //    splits every line of the Picard sweeps into its two elastic row groups.
 template <int D, int N, class PDE, int PREC, bool kAccLds, bool kMfma, int kBFac>
@@ -1566,13 +1619,14 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
       initial_guess<D, N, PDE, float, kBF, BS, kSplit>(P, sq32, sacc32, ureg, dtf, (float)irho, (float)lam,
                                                      (float)mu);
     }
-    if constexpr (PREC == kFP32 && kMfma) {
+    if constexpr (kMfma) {
       float *sacc32b = pair_axes<D, N, BS>() ? sacc32 + M * S::NST : nullptr;
       static_assert(!pair_axes<D, N, BS>() || 2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators");
       MfmaOps<N> mo;
-      load_mfma_ops<N, PDE>(P, dtf, mo);
+      load_mfma_ops<N, PDE, kBF>(P, dtf, mo);
       for (int s = 0; s < full32; s++)
-        picard_sweep_mfma<D, N, PDE, BS>(P, mo, sq32, sacc32, sacc32b, ureg, dtf, (float)irho, (float)lam, (float)mu);
+        picard_sweep_mfma<D, N, PDE, BS, kBF>(P, mo, sq32, sacc32, sacc32b, ureg, dtf, (float)irho, (float)lam,
+                                              (float)mu);
     } else if constexpr (!kSplit && pair_axes<D, N, BS>()) {
       // the FP32 accumulator fills half of region R: the second one takes the other half
       static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");

@@ -57,6 +57,8 @@ KernelSet make_kernel_set() {
   add_variant<D, N, PDE, kFP32, true, true, 2>(k, "fp32-mfma-b2");
   add_variant<D, N, PDE, kBF16, true, false, 1>(k, "bf16-valu-b1");
   add_variant<D, N, PDE, kBF16, true, false, 2>(k, "bf16-valu-b2");
+  add_variant<D, N, PDE, kBF16, true, true, 1>(k, "bf16-mfma-b1");
+  add_variant<D, N, PDE, kBF16, true, true, 2>(k, "bf16-mfma-b2");
   if constexpr (ipow(N + 1, D) > 128) {
     // one or two workgroups per CU: also 512- or 1024-thread blocks (the
     // FP64 and MFMA line phases of these elements do not fit the 128

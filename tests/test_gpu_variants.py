@@ -24,7 +24,7 @@ VARIANTS = {
     "fp64": ["fp64-valu-b1", "fp64-valu-b2", "fp64-valu-hbmacc-b1", "fp64-valu-split", "fp64-valu-hbmacc-split",
              "fp64-valu-groups"],
     "fp32": ["fp32-valu-b1", "fp32-valu-b2", "fp32-mfma-b1", "fp32-mfma-b2", "fp32-valu-split", "fp32-valu-w4"],
-    "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-valu-split", "bf16-valu-w4"],
+    "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-mfma-b1", "bf16-mfma-b2", "bf16-valu-split", "bf16-valu-w4"],
 }
 TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
 CASES = [(pde, N, prec, v) for pde, Ns in (("euler2", range(1, 8)), ("euler", range(1, 8)), ("elastic", range(1, 6)))
