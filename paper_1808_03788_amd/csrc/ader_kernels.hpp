@@ -308,9 +308,11 @@ __device__ __forceinline__ float round_bf16(float x) {
 // kPart (elasticity only) restricts the line to one row group; variable v
 // of the accumulator is held at (v - kAccShift) * VS.  With kHold the n x M
 // results go to held[k * M + v] (registers of the caller) instead of sacc.
+// The accumulator is stored as TA (T, or FP32 partial sums of the FP64
+// residual sweep).
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0,
-          int kAccShift = 0, bool kHold = false>
-__device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int base, T irho, T lam, T mu,
+          int kAccShift = 0, bool kHold = false, typename TA = T>
+__device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int base, T irho, T lam, T mu,
                                          T *held = nullptr) {
   constexpr int n = N + 1, M = PDE::M;
   constexpr int ST = ipow(n, A);
@@ -326,7 +328,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
   for (int k = 0; k < n; k++)
 #pragma unroll
     for (int v = 0; v < M; v++)
-      acc[k][v] = (kAcc && part_writes<kPart>(v)) ? sacc[(v - kAccShift) * VS + base + k * ST] : T(0);
+      acc[k][v] = (kAcc && part_writes<kPart>(v)) ? (T)sacc[(v - kAccShift) * VS + base + k * ST] : T(0);
   if constexpr (!PDE::kElastic) {
     T F[n][M];
 #pragma unroll
@@ -370,7 +372,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, T *sacc, int bas
       if constexpr (kHold)
         held[k * M + v] = acc[k][v];
       else if (part_writes<kPart>(v))
-        sacc[(v - kAccShift) * VS + base + k * ST] = acc[k][v];
+        sacc[(v - kAccShift) * VS + base + k * ST] = (TA)acc[k][v];
     }
 }
 
@@ -422,8 +424,8 @@ __host__ __device__ constexpr int third_axis(int D, int N) {
 // the block takes the velocity rows of every line and the second half the
 // stress rows (whole wavefronts on each side).
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kSplit = false,
-          bool kAcc = (A > 0)>
-__device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho, T lam, T mu) {
+          bool kAcc = (A > 0), typename TA = T>
+__device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, TA *sacc, T irho, T lam, T mu) {
   constexpr int NS = line_slots_count<D, N>(), NST = Shape<D, N>::NST;
   if constexpr (kSplit) {
     static_assert(BS == 2 * NS && PDE::kElastic, "two threads per line");
@@ -438,7 +440,8 @@ __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, T *sacc, T irho,
   } else {
     for (int L = threadIdx.x; L < NS; L += BS) {
       const int base = slot_base<D, N, A>(L);
-      if (base != kEmptySlot) line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc>(P, sq, sacc, base, irho, lam, mu);
+      if (base != kEmptySlot)
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc, 0, 0, false, TA>(P, sq, sacc, base, irho, lam, mu);
     }
   }
 }
@@ -514,30 +517,58 @@ __device__ __forceinline__ double opTrow<double>(PArg &P, int l) { return cload(
 template <>
 __device__ __forceinline__ float opTrow<float>(PArg &P, int l) { return cload(&P.sw->Trowf[l]); }
 
-template <int D, int N, class PDE, typename T, typename TO, int BS, bool kTwo = false>
-__device__ __forceinline__ void time_phase(PArg &P, const T *sacc, TO *qout, const double *ureg, T dt,
-                                           const T *sacc2 = nullptr) {
+template <int D, int N, class PDE, typename T, typename TO, int BS, bool kTwo = false, typename TA = T>
+__device__ __forceinline__ void time_phase(PArg &P, const TA *sacc, TO *qout, const double *ureg, T dt,
+                                           const TA *sacc2 = nullptr) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST;
   constexpr int NU = TimeItems<D, N, M, BS>::value;
+  // a wider iterate written over narrower partial sums (the FP64 iterate of
+  // the residual sweep over its FP32 accumulators) overlaps the values other
+  // threads still read: every thread reads first, then writes after a barrier
+  constexpr bool kWiden = sizeof(TO) > sizeof(TA);
+  T rr[kWiden ? NU : 1][n];
 #pragma unroll
   for (int r = 0; r < NU; r++) {
     const int i = threadIdx.x + r * BS;
+    const int rs = kWiden ? r : 0;
     if (i < M * ND) {
       const int v = i / ND, k = i - v * ND;
-      const T u0 = (T)ureg[r];
-      T rr[n];
 #pragma unroll
       for (int j = 0; j < n; j++) {
-        rr[j] = sacc[v * NST + j * ND + k];
-        if constexpr (kTwo) rr[j] += sacc2[v * NST + j * ND + k];
+        rr[rs][j] = (T)sacc[v * NST + j * ND + k];
+        if constexpr (kTwo) rr[rs][j] += (T)sacc2[v * NST + j * ND + k];
       }
+    }
+    if constexpr (!kWiden) {
+      if (i < M * ND) {
+        const int v = i / ND, k = i - v * ND;
+        const T u0 = (T)ureg[r];
 #pragma unroll
-      for (int l = 0; l < n; l++) {
-        T a = T(0);
+        for (int l = 0; l < n; l++) {
+          T a = T(0);
 #pragma unroll
-        for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[j];
-        qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
+          for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[0][j];
+          qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
+        }
+      }
+    }
+  }
+  if constexpr (kWiden) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < NU; r++) {
+      const int i = threadIdx.x + r * BS;
+      if (i < M * ND) {
+        const int v = i / ND, k = i - v * ND;
+        const T u0 = (T)ureg[r];
+#pragma unroll
+        for (int l = 0; l < n; l++) {
+          T a = T(0);
+#pragma unroll
+          for (int j = 0; j < n; j++) a += opT<T>(P, l * kMaxN + j) * rr[r][j];
+          qout[v * NST + l * ND + k] = (TO)(u0 + dt * a);
+        }
       }
     }
   }
@@ -575,18 +606,20 @@ __host__ __device__ constexpr int pair_b() { return third_axis(D, N) == 2 || D <
 // The paired axes at the same time: the first half of the block stores the
 // lines of axis pair_a into sacc, the second half those of axis pair_b into
 // sacc2 (the time phase adds the two).
-template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS>
-__device__ __forceinline__ void rhs_pair(PArg &P, const TQ *sq, T *sacc, T *sacc2, T irho, T lam, T mu) {
+template <int D, int N, class PDE, typename T, typename TQ, bool kRoundBF, int BS, typename TA = T>
+__device__ __forceinline__ void rhs_pair(PArg &P, const TQ *sq, TA *sacc, TA *sacc2, T irho, T lam, T mu) {
   constexpr int NS = line_slots_count<D, N>(), NST = Shape<D, N>::NST;
   constexpr int a = pair_a<D, N>(), b = pair_b<D, N>();
   static_assert(pair_axes<D, N, BS>(), "two halves of whole wavefronts");
   const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
   if (half == 0) {
     const int base = slot_base<D, N, a>(L);
-    if (base != kEmptySlot) line_rhs<D, N, PDE, a, T, TQ, kRoundBF, NST, false>(P, sq, sacc, base, irho, lam, mu);
+    if (base != kEmptySlot)
+      line_rhs<D, N, PDE, a, T, TQ, kRoundBF, NST, false, 0, 0, false, TA>(P, sq, sacc, base, irho, lam, mu);
   } else if (half == 1) {
     const int base = slot_base<D, N, b>(L);
-    if (base != kEmptySlot) line_rhs<D, N, PDE, b, T, TQ, kRoundBF, NST, false>(P, sq, sacc2, base, irho, lam, mu);
+    if (base != kEmptySlot)
+      line_rhs<D, N, PDE, b, T, TQ, kRoundBF, NST, false, 0, 0, false, TA>(P, sq, sacc2, base, irho, lam, mu);
   }
 }
 
@@ -627,35 +660,36 @@ __device__ __forceinline__ void rhs_pair_held(PArg &P, const TQ *sq, T *sacc, T 
 // sacc.
 constexpr int kPairTwo = 1, kPairHeld = 2;
 template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kRoundBF, int BS, bool kSplit = false,
-          int kPair = 0>
-__device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, T *sacc, TO *qout,
-                                             const double *ureg, T dt, T irho, T lam, T mu, T *sacc2 = nullptr) {
+          int kPair = 0, typename TA = T>
+__device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, TA *sacc, TO *qout,
+                                             const double *ureg, T dt, T irho, T lam, T mu, TA *sacc2 = nullptr) {
+  static_assert(std::is_same<TA, T>::value || (!kSplit && kPair != kPairHeld), "narrow accumulators: line phases");
   if constexpr (kPair != 0) {
     static_assert(!kSplit, "one thread per line");
     if constexpr (kPair == kPairTwo)
-      rhs_pair<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, sacc2, irho, lam, mu);
+      rhs_pair<D, N, PDE, T, TQ, kRoundBF, BS, TA>(P, sq, sacc, sacc2, irho, lam, mu);
     else
       rhs_pair_held<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 2) {
-      rhs_axis<D, N, PDE, third_axis(D, N), T, TQ, kRoundBF, BS, false, true>(P, sq, sacc, irho, lam, mu);
+      rhs_axis<D, N, PDE, third_axis(D, N), T, TQ, kRoundBF, BS, false, true, TA>(P, sq, sacc, irho, lam, mu);
       __syncthreads();
     }
-    time_phase<D, N, PDE, T, TO, BS, kPair == kPairTwo>(P, sacc, qout, ureg, dt, sacc2);
+    time_phase<D, N, PDE, T, TO, BS, kPair == kPairTwo, TA>(P, sacc, qout, ureg, dt, sacc2);
     __syncthreads();
     return;
   }
-  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
+  rhs_axis<D, N, PDE, 0, T, TQ, kRoundBF, BS, kSplit, false, TA>(P, sq, sacc, irho, lam, mu);
   __syncthreads();
   if constexpr (D > 1) {
-    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 1, T, TQ, kRoundBF, BS, kSplit, true, TA>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
   if constexpr (D > 2) {
-    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS, kSplit>(P, sq, sacc, irho, lam, mu);
+    rhs_axis<D, N, PDE, 2, T, TQ, kRoundBF, BS, kSplit, true, TA>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
   }
-  time_phase<D, N, PDE, T, TO, BS>(P, sacc, qout, ureg, dt);
+  time_phase<D, N, PDE, T, TO, BS, false, TA>(P, sacc, qout, ureg, dt);
   __syncthreads();
 }
 
@@ -1640,15 +1674,23 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
         picard_sweep<D, N, PDE, float, float, float, kBF, BS, kSplit>(P, sq32, sacc32, sq32, ureg, dtf,
                                                                   (float)irho, (float)lam, (float)mu);
     }
-    // FP64 residual sweep from the FP32 iterate; the new iterate overwrites
-    // the FP64 accumulator in place
-    // paired with axis 1 held in registers where an axis phase spans more
-    // than one wavefront (at N = 3 in 3-D the extra registers cost this
-    // kernel a wavefront of occupancy and the sweep was slower)
-    constexpr int kPairR =
-        (!kSplit && kBFac != kWide && pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairHeld : 0;
-    picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit, kPairR>(P, sq32, sR, sR, ureg, dt, irho, lam,
-                                                                             mu);
+    // FP64 residual sweep from the FP32 iterate, into region R
+    if constexpr (!kSplit && kBFac != kWide) {
+      // FP64 arithmetic with the partial sums stored in FP32: they enter the
+      // iterate multiplied by dt, so their rounding is 2^-24 of the one-step
+      // change, not of the state; two FP32 accumulators fill region R (axes
+      // paired where an axis phase spans more than one wavefront), and the
+      // time phase writes the FP64 iterate over them
+      float *ra = (float *)sR, *rb = ra + M * S::NST;
+      static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");
+      constexpr int kPairR = (pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairTwo : 0;
+      picard_sweep<D, N, PDE, double, float, double, false, BS, false, kPairR, float>(P, sq32, ra, sR, ureg, dt, irho,
+                                                                                      lam, mu, rb);
+    } else {
+      // FP64 accumulator, unpaired (the elasticity row-group split, and the
+      // 512/1024-thread blocks whose 128 registers hold no more)
+      picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
+    }
     predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
   }
 }
