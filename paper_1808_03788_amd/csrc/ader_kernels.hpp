@@ -1996,6 +1996,19 @@ struct UpdArgs {
   const double *mat;   // elasticity: [E][3] material
 };
 
+// The wave-speed maximum of a problem is collected in kSmaxSlots slots, one
+// 128-byte line apart: each workgroup of the update or time-step kernel
+// takes the slot of its tile or row, so that the atomics of many workgroups
+// do not queue on one address (one address per problem serialises them at
+// about 13 ns each, which bounded the update at 262144 tiles).  The
+// time-step finalisation takes the maximum over the slots and clears them.
+constexpr int kSmaxSlots = 32;
+constexpr int kSmaxStride = 16;  // unsigned long longs from one slot to the next
+constexpr int kSmaxPerProblem = kSmaxSlots * kSmaxStride;
+__device__ __forceinline__ unsigned long long *smax_slot(unsigned long long *bits, int pidx, int64_t key) {
+  return bits + (int64_t)pidx * kSmaxPerProblem + (key & (kSmaxSlots - 1)) * kSmaxStride;
+}
+
 // u^{n+1} = u* - dt sum_A (1/h_A) [ L1_kA G_+face + L0_kA G_-face ]  (FP64
 // arithmetic; face integrals stored as GT).  A tile is a chunk of
 // upd_elems() whole elements of the x-row (iy, iz).  The workgroup first
@@ -2212,7 +2225,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const Ro
         for (int off = 32; off > 0; off >>= 1) smx = fmax(smx, __shfl_xor(smx, off, 64));
         if (__any(badm)) bad_any = 1;  // wave 0 only; the other waves wrote bad_any before the barrier
         if (threadIdx.x == 0) {
-          atomicMax(smax_bits + t.pidx, (unsigned long long)__double_as_longlong(smx));
+          atomicMax(smax_slot(smax_bits, t.pidx, tile), (unsigned long long)__double_as_longlong(smx));
           if (bad_any) atomicOr(err, 1);
         }
       }
@@ -2228,15 +2241,16 @@ struct CflArgs {
   double h[3];
   int64_t u_off;                  // offset of the problem's u in the state buffer
   const double *mat;
-  int pidx;                       // problem index: smax[pidx] collects its maximum
+  int pidx;                       // problem index: the slots smax_slot(., pidx, .) collect its maximum
   double *summ;                   // optional [E][M][2]: min and max of every variable per element
 };
 
 // Per-element wave speed S_e = sum_A (max_k |lambda_A(u_k)|) / h_A and its
 // maximum over the mesh.  A tile is one x-row of elements (tile = iy + ny iz):
 // the workgroup walks it one wavefront per element at a time and issues a
-// single atomicMax on the bit pattern of the row maximum (positive doubles
-// order like their bits, so the result does not depend on the order).
+// single atomicMax on the bit pattern of the row maximum into the row's slot
+// (positive doubles order like their bits, so the result does not depend on
+// the order).
 template <int D, int N, class PDE>
 __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const double *u,
                                         unsigned long long *smax_bits, int *err, double *red, int *bad_any) {
@@ -2305,7 +2319,7 @@ __device__ __forceinline__ void cfl_row(const CflArgs &C, int64_t row, const dou
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int i = 1; i < kBlock / 64; i++) m = fmax(m, red[i]);
-    atomicMax(smax_bits + C.pidx, (unsigned long long)__double_as_longlong(m));
+    atomicMax(smax_slot(smax_bits, C.pidx, row), (unsigned long long)__double_as_longlong(m));
     if (*bad_any) atomicOr(err, 1);
     *bad_any = 0;
   }

@@ -92,8 +92,8 @@ struct ader_ctx {
   int *flags = nullptr;                                  // device [total elements]
   int64_t total_e = 0;
   std::vector<double> tend_host;                         // values held by tend
-  unsigned long long *smax = nullptr;                      // device [nprob], time-step kernel maxima
-  unsigned long long *smax_f = nullptr;                    // device [nprob], maxima taken by the update
+  unsigned long long *smax = nullptr;    // device [nprob][kSmaxPerProblem] slots, time-step kernel maxima
+  unsigned long long *smax_f = nullptr;  // device, the same slots: maxima taken by the update
   const double *fused_u = nullptr;  // state buffer whose maxima smax_f holds (written by the last step)
   int *hist_ok = nullptr;           // device [1]: the guess-3 history belongs to the state in hist_u
   double *dtprev = nullptr;         // device [nprob]: step of the last completed step
@@ -180,6 +180,12 @@ ader_status validate(ader_ctx *c, const ader_problem &d, int i) {
 // time-step kernel, by an earlier step, or here) every problem takes dt = 0,
 // independently of thread timing.
 constexpr int kFinBlock = 256;
+// Maximum over the slots of problem i (bit patterns of positive doubles).
+__device__ __forceinline__ double slots_max(unsigned long long *smax, int i) {
+  unsigned long long m = 0ull;
+  for (int k = 0; k < kSmaxSlots; k++) m = max(m, *smax_slot(smax, i, k));
+  return __longlong_as_double((long long)m);
+}
 // smax is the buffer of maxima this step uses; both it and smax_f (the
 // update's buffer, filled again by this step's update) are cleared.
 __global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax, unsigned long long *smax_f,
@@ -188,14 +194,16 @@ __global__ void __launch_bounds__(kFinBlock) k_finalize(unsigned long long *smax
   const int prior = *err;  // written before this kernel (it writes err only after the barrier)
   int bad = 0;
   for (int i = threadIdx.x; i < np; i += kFinBlock) {
-    const double S = __longlong_as_double((long long)smax[i]);
+    const double S = slots_max(smax, i);
     if (!(S > 0.0) || isinf(S)) bad = 1;
   }
   const bool stop = __syncthreads_or(bad) || prior;
   for (int i = threadIdx.x; i < np; i += kFinBlock) {
-    const double S = __longlong_as_double((long long)smax[i]);
-    smax[i] = 0ull;
-    smax_f[i] = 0ull;
+    const double S = slots_max(smax, i);
+    for (int k = 0; k < kSmaxSlots; k++) {
+      *smax_slot(smax, i, k) = 0ull;
+      *smax_slot(smax_f, i, k) = 0ull;
+    }
     double d = stop ? 0.0 : coef[i] / S;
     double tn = t[i] + d;
     if (clip) {
@@ -908,8 +916,9 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   if ((st = dalloc(c, (void **)&c->dt, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->t, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->tnext, nprob * sizeof(double)))) return bail(st);
-  if ((st = dalloc(c, (void **)&c->smax, nprob * sizeof(unsigned long long)))) return bail(st);
-  if ((st = dalloc(c, (void **)&c->smax_f, nprob * sizeof(unsigned long long)))) return bail(st);
+  const size_t smax_bytes = (size_t)nprob * kSmaxPerProblem * sizeof(unsigned long long);
+  if ((st = dalloc(c, (void **)&c->smax, smax_bytes))) return bail(st);
+  if ((st = dalloc(c, (void **)&c->smax_f, smax_bytes))) return bail(st);
   if ((st = dalloc(c, (void **)&c->dtprev, nprob * sizeof(double)))) return bail(st);
   if ((st = dalloc(c, (void **)&c->hist_ok, sizeof(int)))) return bail(st);
   {
@@ -926,8 +935,7 @@ ader_status ader_create(const ader_problem *probs, int32_t nprob, void *hip_stre
   if (hipMemset(c->dt, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->t, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->tnext, 0, nprob * sizeof(double)) != hipSuccess ||
-      hipMemset(c->smax, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
-      hipMemset(c->smax_f, 0, nprob * sizeof(unsigned long long)) != hipSuccess ||
+      hipMemset(c->smax, 0, smax_bytes) != hipSuccess || hipMemset(c->smax_f, 0, smax_bytes) != hipSuccess ||
       hipMemset(c->dtprev, 0, nprob * sizeof(double)) != hipSuccess ||
       hipMemset(c->hist_ok, 0, sizeof(int)) != hipSuccess ||
       hipMemset(c->err, 0, sizeof(int)) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
@@ -1125,7 +1133,8 @@ ader_status ader_run(ader_ctx *c, double *u, const double *t_end_host, int32_t n
     // the replay's first step needs the maxima of u in smax_f
     c->fused_u = nullptr;
     const int np = (int)c->P.size();
-    hipLaunchKernelGGL(k_zero_u64, dim3((np + 255) / 256), dim3(256), 0, c->stream, c->smax_f, np);
+    hipLaunchKernelGGL(k_zero_u64, dim3((np * kSmaxPerProblem + 255) / 256), dim3(256), 0, c->stream, c->smax_f,
+                       np * kSmaxPerProblem);
     HIP_OR_FAIL(c, hipGetLastError());
     if ((st = run_maxima(c, u, c->smax_f))) return st;
   }
