@@ -7,9 +7,12 @@ N = 1..5 (the split variants, two threads per line by elastic row group,
 and the FP64 row-group sweep exist for elasticity only; the factor-2 FP32
 and BF16 variants run axes 0 and 1 at the same time wherever the block
 holds both sets of lines, which covers 2-D, and 3-D up to N = 4) and
-held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-2
-(relative L2 after three steps).  A variant that does not fit the problem's
-LDS budget is not offered by the library and the case is skipped.
+held to the oracle: FP64 variants to 1e-12, FP32 to 1e-6, BF16 to 1e-4 on
+Euler and 1e-2 on elasticity (relative L2 after three steps; max-norm ten
+times that).  The BF16 MFMA variants contract on v_mfma_f32_4x4x4bf16_1k
+with the operator split into two bfloat16 parts.  A variant that does not
+fit the problem's LDS budget is not offered by the library and the case is
+skipped.
 """
 import os
 import sys
@@ -27,6 +30,15 @@ VARIANTS = {
     "bf16": ["bf16-valu-b1", "bf16-valu-b2", "bf16-mfma-b1", "bf16-mfma-b2", "bf16-valu-split", "bf16-valu-w4"],
 }
 TOL = {"fp64": 1e-12, "fp32": 1e-6, "bf16": 1e-2}
+# BF16 on Euler: 1e-4 (measured <= 2.3e-5); elasticity keeps 1e-2 (measured
+# 7.7e-3): its velocities start at rest and after three steps are small
+# against the bfloat16-rounded stress values they are computed from
+
+
+def tol(pde, prec):
+    return 1e-4 if prec == "bf16" and pde != "elastic" else TOL[prec]
+
+
 CASES = [(pde, N, prec, v) for pde, Ns in (("euler2", range(1, 8)), ("euler", range(1, 8)), ("elastic", range(1, 6)))
          for N in Ns for prec, vs in VARIANTS.items() for v in vs]
 
@@ -99,5 +111,5 @@ def test_forced_variant_vs_oracle(A, orc, pde, N, prec, variant):
     err = I.rel_l2(prob, ug, ref)
     ei = I.rel_linf(ug, ref)
     say(f"  rel_l2={err:.3e} rel_linf={ei:.3e}")
-    assert err <= TOL[prec], (variant, N, err)
-    assert ei <= 10 * TOL[prec], (variant, N, "linf", ei)
+    assert err <= tol(pde, prec), (variant, N, err)
+    assert ei <= 10 * tol(pde, prec), (variant, N, "linf", ei)
