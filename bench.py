@@ -45,7 +45,7 @@ PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp32_valu_unpacked": 78.6,
 C_F, C_B, C_R = 28, 48, 85
 
 
-def survey_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False) -> dict:
+def work_model_flops(d: int, N: int, m: int, sweeps: int, elastic: bool = False) -> dict:
     """Algorithmic (sum-factorised) flops per element of one step, split by
     stage: a Picard sweep counts, per space-time node, the pointwise flux
     (c_F) or B-term (c_B), d axis contractions and one time contraction at
@@ -71,7 +71,7 @@ def precision_split(probs, prec: str) -> tuple:
     FP32 (or BF16 inputs) and sweep P plus the outputs in FP64."""
     lo = hi = 0.0
     for p in probs:
-        f = survey_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic")
+        f = work_model_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic")
         if prec == "fp64":
             hi += p.E * f["predictor"]
         else:
@@ -438,7 +438,7 @@ def lds_evidence():
 
 def roof(res, prec, workload_sized=True, traffic=None):
     """Roofline of the dominant kernel (the predictor) per the algorithmic
-    work model survey_flops: reduced-precision sweeps at the FP32 (BF16)
+    work model work_model_flops: reduced-precision sweeps at the FP32 (BF16)
     matrix peak, the FP64 sweep and outputs at the FP64 peak; `peak` is the
     blend of the two for this workload's mix, so achieved/peak = time at
     the peaks / measured time."""
@@ -480,7 +480,7 @@ def step_roofline(res, prec, ms_per_step):
     """Whole-step bound: max(time at the dtype peaks of all step flops,
     algorithmic bytes 16 m + 4 d m s per DOF at 8 TB/s)."""
     lo, hi = precision_split(res["probs"], prec)
-    hi += sum(p.E * survey_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic")["corrector"]
+    hi += sum(p.E * work_model_flops(p.dim, p.N, p.m, sweeps_of(p), p.pde == "elastic")["corrector"]
               for p in res["probs"])
     t_f = roof_time_ms(lo, hi, prec)
     s = 8 if prec == "fp64" else 4

@@ -35,17 +35,17 @@ def test_flop_and_byte_models():
     assert bench.sweeps_of(P) == 3
 
 
-def test_survey_flop_model_per_dof():
+def test_work_model_flops_per_dof():
     """The algorithmic work model reproduces the per-DOF step figures of the
     work model it states (Euler N = 2..6 with N+1 sweeps: 2.25k, 4.15k,
     7.08k, 11.3k, 17.0k flop per DOF; elasticity N = 5: about 19.5k)."""
     import bench
     want = {2: 2.25e3, 3: 4.15e3, 4: 7.08e3, 5: 11.3e3, 6: 17.0e3}
     for N, f in want.items():
-        s = bench.survey_flops(3, N, 5, N + 1)
+        s = bench.work_model_flops(3, N, 5, N + 1)
         per_dof = (s["predictor"] + s["corrector"]) / (N + 1) ** 3
         assert abs(per_dof - f) <= 0.01 * f, (N, per_dof)
-    s = bench.survey_flops(3, 5, 9, 6, elastic=True)
+    s = bench.work_model_flops(3, 5, 9, 6, elastic=True)
     assert abs((s["predictor"] + s["corrector"]) / 216 - 19.5e3) <= 0.02 * 19.5e3
 
 
@@ -57,7 +57,7 @@ def test_split_roofline_time():
     class P:
         dim, N, m, E, pde, picard, guess = 3, 4, 5, 262144, "euler", 0, 0
     lo, hi = bench.precision_split([P], "fp32")
-    s = bench.survey_flops(3, 4, 5, 5)
+    s = bench.work_model_flops(3, 4, 5, 5)
     assert lo == P.E * 4 * s["sweep"] and hi == P.E * (s["sweep"] + s["outputs"])
     t = bench.roof_time_ms(lo, hi, "fp32")
     assert abs(t - (lo / 157.3e12 + hi / 78.6e12) * 1e3) < 1e-12
