@@ -116,21 +116,26 @@ def check_sampled(orc, prob, u0, ug, dt, picks, tol, what, inc_tol=None):
 
 
 CASES = [
-    ("density", "fp32", None),
-    ("elastic", "fp64", (0.5, 0.5, 0.375)),
-    ("elastic", "fp32", (0.5, 0.5, 0.375)),
-    ("elastic", "bf16", (0.5, 0.5, 0.375)),
-    ("fourier", "fp64", None),
-    ("fourier", "fp32", None),
+    ("density", "fp32", None, 0),
+    ("density", "fp32", None, 1),
+    ("elastic", "fp64", (0.5, 0.5, 0.375), 0),
+    ("elastic", "fp32", (0.5, 0.5, 0.375), 0),
+    ("elastic", "fp32", (0.5, 0.5, 0.375), 1),
+    ("elastic", "bf16", (0.5, 0.5, 0.375), 0),
+    ("fourier", "fp64", None, 0),
+    ("fourier", "fp32", None, 0),
 ]
 
 
-@pytest.mark.parametrize("workload,prec,hot", CASES, ids=[f"{c[0]}-{c[1]}" for c in CASES])
-def test_full_size_sampled(A, orc, workload, prec, hot):
+@pytest.mark.parametrize("workload,prec,hot,face_avg", CASES,
+                         ids=[f"{c[0]}-{c[1]}" + ("-faceavg" if c[3] else "") for c in CASES])
+def test_full_size_sampled(A, orc, workload, prec, hot, face_avg):
+    """face_avg: face integrals from time-averaged traces (the oracle's
+    sub-mesh step uses the same option)."""
     import torch
-    probs, inits, desc = bench.make_workload(workload, prec, I, None, None, 0, 0, 0)
+    probs, inits, desc = bench.make_workload(workload, prec, I, None, None, 0, 0, face_avg)
     prob, u0 = probs[0], inits[0]
-    say(f"[full size] {workload} {prec}: {desc}")
+    say(f"[full size] {workload} {prec} face_avg={face_avg}: {desc}")
     ctx = A.Context([prob])
     try:
         u = ctx.upload([u0])
