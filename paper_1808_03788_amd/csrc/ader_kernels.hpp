@@ -663,7 +663,7 @@ template <int D, int N, class PDE, typename T, typename TQ, typename TO, bool kR
           int kPair = 0, typename TA = T>
 __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, TA *sacc, TO *qout,
                                              const double *ureg, T dt, T irho, T lam, T mu, TA *sacc2 = nullptr) {
-  static_assert(std::is_same<TA, T>::value || (!kSplit && kPair != kPairHeld), "narrow accumulators: line phases");
+  static_assert(std::is_same<TA, T>::value || kPair != kPairHeld, "narrow accumulators are not held");
   if constexpr (kPair != 0) {
     static_assert(!kSplit, "one thread per line");
     if constexpr (kPair == kPairTwo)
@@ -1675,7 +1675,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
                                                                   (float)irho, (float)lam, (float)mu);
     }
     // FP64 residual sweep from the FP32 iterate, into region R
-    if constexpr (!kSplit && kBFac != kWide) {
+    if constexpr (kBFac != kWide) {
       // FP64 arithmetic with the partial sums stored in FP32: they enter the
       // iterate multiplied by dt, so their rounding is 2^-24 of the one-step
       // change, not of the state; two FP32 accumulators fill region R (axes
@@ -1683,12 +1683,12 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
       // time phase writes the FP64 iterate over them
       float *ra = (float *)sR, *rb = ra + M * S::NST;
       static_assert(2 * M * S::NST * sizeof(float) <= L::R, "two FP32 accumulators in region R");
-      constexpr int kPairR = (pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairTwo : 0;
-      picard_sweep<D, N, PDE, double, float, double, false, BS, false, kPairR, float>(P, sq32, ra, sR, ureg, dt, irho,
-                                                                                      lam, mu, rb);
+      constexpr int kPairR = (!kSplit && pair_axes<D, N, BS>() && ipow(N + 1, D) > 64) ? kPairTwo : 0;
+      picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit, kPairR, float>(P, sq32, ra, sR, ureg, dt,
+                                                                                       irho, lam, mu, rb);
     } else {
-      // FP64 accumulator, unpaired (the elasticity row-group split, and the
-      // 512/1024-thread blocks whose 128 registers hold no more)
+      // FP64 accumulator, unpaired (the 512/1024-thread blocks, whose 128
+      // registers hold no more)
       picard_sweep<D, N, PDE, double, float, double, false, BS, kSplit>(P, sq32, sR, sR, ureg, dt, irho, lam, mu);
     }
     predictor_outputs<D, N, PDE, float, BS, kSplit>(P, sR, (double *)smem_raw, ue, ureg, dt, e, qo, irho, lam, mu);
