@@ -2027,11 +2027,14 @@ __device__ __forceinline__ unsigned long long *smax_slot(unsigned long long *bit
 // per-element quantity as k_cfl), so a step of ader_step does not read u
 // again for it.
 //
-// Elements per tile: at most 512 nodes, and at most 32 KB of staged FP64
-// face values (2D faces of M * n^(D-1) values per element).
+// Elements per tile: at most 256 nodes for Euler and 512 for elasticity
+// (measured: Euler 64^3 N=4 0.79 -> 0.67 ms from 512 to 256 nodes,
+// elasticity 48^3 N=5 0.93 -> 1.13 ms, one 216-node element per tile), and
+// at most 32 KB of staged FP64 face values (2D faces of M * n^(D-1) values
+// per element).
 __host__ __device__ constexpr int upd_elems(int D, int N, int M) {
   const int nd = ipow(N + 1, D), nf = ipow(N + 1, D - 1);
-  const int by_nodes = 512 / nd, by_lds = 32768 / (2 * D * M * nf * 8);
+  const int by_nodes = (M >= 9 ? 512 : 256) / nd, by_lds = 32768 / (2 * D * M * nf * 8);
   const int e = by_nodes < by_lds ? by_nodes : by_lds;
   return e > 0 ? e : 1;
 }
