@@ -1546,7 +1546,7 @@ __device__ __forceinline__ void predictor_element(PArg &P, int64_t e, const doub
   static_assert(!kSplit || (PDE::kElastic && !kMfma), "row-group split: elasticity, VALU sweeps");
   using S = Shape<D, N>;
   using L = PredLds<D, N, PDE::M, PREC>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND;
+  constexpr int M = PDE::M, ND = S::ND;
   double irho = 0.0, lam = 0.0, mu = 0.0;
   if constexpr (PDE::kElastic) {
     irho = 1.0 / P.mat[3 * e + 0];

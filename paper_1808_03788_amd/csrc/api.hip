@@ -276,8 +276,6 @@ __global__ void k_totals_final(const double *partial, int nblk, int m, double *o
   out[v] = s;
 }
 
-int64_t blocks_for(int64_t work) { return (work + kBlock - 1) / kBlock; }
-
 // Scratch of ader_totals_noalloc: the per-block partial sums of
 // k_totals_partial, kTotBlocks x (at most 9 variables) doubles (36 KB).  Each
 // device holds its own copy until the process ends.  In host code the name
