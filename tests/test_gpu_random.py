@@ -11,10 +11,8 @@ rho c_p of the element); then, per variable, the discrete L2 norm of the
 difference divided by max(its own norm, 1e-3 x the largest variable norm).
 The floor matters for variables that vanish by symmetry (a single element
 across an axis with a centred pulse): both sides then hold rounding noise
-only.  Bounds: FP64 1e-12; FP32 sweeps 1e-6 for Euler and 1e-5 for
-elasticity, whose velocities three steps after rest are small against the
-FP32-rounded stress terms they are computed from (the fixed elasticity tests
-with developed velocity fields hold 1e-6).
+only.  Bounds: FP64 1e-12; FP32 sweeps 1e-6 for both systems (the elastic
+velocities, small three steps after rest, are compared in stress units).
 """
 import sys
 
