@@ -2072,6 +2072,24 @@ __device__ __forceinline__ void row_run_max(double (&x)[D], int loc, int lane) {
   }
 }
 
+// Copy of `count` face values (whole elements of EB values) from HBM into
+// LDS, in 16-byte pieces where an element's values fill whole pieces (then
+// every element, and every LDS chunk of whole elements, starts 16-byte
+// aligned), else value by value.
+typedef double d2v __attribute__((ext_vector_type(2)));
+template <typename GT, int EB>
+__device__ __forceinline__ void stage_chunk(GT *dst, const __attribute__((address_space(1))) GT *src, int count) {
+  if constexpr ((EB * sizeof(GT)) % 16 == 0) {
+    using V = typename std::conditional<sizeof(GT) == 4, f4v, d2v>::type;
+    constexpr int W = 16 / sizeof(GT);
+    const auto *vs = (const __attribute__((address_space(1))) V *)src;
+    V *vd = (V *)dst;
+    for (int i = threadIdx.x; i < count / W; i += kBlock) vd[i] = vs[i];
+  } else {
+    for (int i = threadIdx.x; i < count; i += kBlock) dst[i] = src[i];
+  }
+}
+
 template <int D, int N, class PDE, typename GT>
 __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const RowTile *tiles, int64_t ntiles,
                                                    double *u, const double *dt, unsigned long long *smax_bits,
@@ -2081,7 +2099,7 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const Ro
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
   constexpr int EPT = L::EPT, EB = L::EB;
   constexpr int ROUNDS = (EPT * ND + kBlock - 1) / kBlock;
-  __shared__ GT sg[L::SIZE];
+  __shared__ __align__(16) GT sg[L::SIZE];
   __shared__ double coef[2][D][n];  // (1/h_A) L1[k], -+(1/h_A) L0[k]
   __shared__ double lam[EPT][D];    // per element of the tile: max over its nodes of lambda_A
   __shared__ int bad_any;
@@ -2123,13 +2141,13 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const Ro
       const auto *gx = as_global((const GT *)U.GL[0]);
       const int64_t exm = erow + (e0 == 0 ? nx - 1 : e0 - 1);  // lower x neighbour of the first element
       if constexpr (PDE::kConservative) {
-        for (int i = threadIdx.x; i < EB; i += kBlock) sg[i] = gx[exm * EB + i];
-        for (int i = threadIdx.x; i < ne * EB; i += kBlock) sg[EB + i] = gx[(erow + e0) * EB + i];
+        stage_chunk<GT, EB>(sg, gx + exm * EB, EB);
+        stage_chunk<GT, EB>(sg + EB, gx + (erow + e0) * EB, ne * EB);
       } else {
         const auto *gxr = as_global((const GT *)U.GR[0]);
-        for (int i = threadIdx.x; i < ne * EB; i += kBlock) sg[i] = gx[(erow + e0) * EB + i];
-        for (int i = threadIdx.x; i < EB; i += kBlock) sg[EPT * EB + i] = gxr[exm * EB + i];
-        for (int i = threadIdx.x; i < (ne - 1) * EB; i += kBlock) sg[EPT * EB + EB + i] = gxr[(erow + e0) * EB + i];
+        stage_chunk<GT, EB>(sg, gx + (erow + e0) * EB, ne * EB);
+        stage_chunk<GT, EB>(sg + EPT * EB, gxr + exm * EB, EB);
+        stage_chunk<GT, EB>(sg + EPT * EB + EB, gxr + (erow + e0) * EB, (ne - 1) * EB);
       }
 #pragma unroll
       for (int A = 1; A < D; A++) {
@@ -2138,10 +2156,8 @@ __global__ void __launch_bounds__(kBlock) k_update(const UpdArgs *args, const Ro
         const int jy = (A == 1) ? (iy == 0 ? ny - 1 : iy - 1) : iy;
         const int jz = (A == 2) ? (iz == 0 ? nz - 1 : iz - 1) : iz;
         const int64_t enb = (int64_t)nx * (jy + (int64_t)ny * jz) + e0;
-        for (int i = threadIdx.x; i < ne * EB; i += kBlock) {
-          sg[L::own(A, 0) + i] = ga[(erow + e0) * EB + i];
-          sg[L::nbr(A, 0) + i] = gn[enb * EB + i];
-        }
+        stage_chunk<GT, EB>(sg + L::own(A, 0), ga + (erow + e0) * EB, ne * EB);
+        stage_chunk<GT, EB>(sg + L::nbr(A, 0), gn + enb * EB, ne * EB);
       }
     }
     __syncthreads();
