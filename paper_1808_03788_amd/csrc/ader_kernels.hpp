@@ -1362,7 +1362,8 @@ __device__ __forceinline__ void elastic_volume_update(PArg &P, const double *QB,
 // trace_s(v, l0, face node) = sum_j phi_j(s) q(v, l0, node with k_A = j),
 // computed in FP64 and stored as TT.  One thread per (l0, face node) pair
 // and variable group; consecutive threads store consecutive trace values.
-template <int D, int N, class PDE, int A, typename TT, int BS>
+// The BS threads from T0 on take part.
+template <int D, int N, class PDE, int A, typename TT, int BS, int T0 = 0>
 __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
@@ -1370,7 +1371,7 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
   using SP = Split<ND, M, BS>;
   TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(M * ND);
   TT *t1 = (TT *)P.trace[A][1] + e * (int64_t)(M * ND);
-  for (int it = threadIdx.x; it < ND * SP::VG; it += BS) {
+  for (int it = (int)threadIdx.x - T0; it < ND * SP::VG; it += BS) {
     const int g = it / ND, t = it - g * ND;  // t = l0 * NF + kf
     const int l0 = t / NF, kf = t - l0 * NF;
     const int base = l0 * ND + kf % ST + (kf / ST) * ST * n;
@@ -1467,14 +1468,28 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
   if (qo)
     for (int i = threadIdx.x; i < M * NST; i += BS) qo[i] = qf[i];
   if (P.guess == 3) write_history<D, N, PDE, TT, BS>(P, qf, e);
-  if (!P.face_avg) {
+  double *us = P.ustar + e * (int64_t)(M * ND);
+  // Euler with two halves of whole wavefronts: the traces on the second
+  // half while the first computes the time-integrated fluxes (both only
+  // read qf)
+  constexpr int HB = BS / 2;
+  constexpr bool kHalves = !PDE::kElastic && N > 0 && HB % 64 == 0 && HB >= ND;
+  if (kHalves && !P.face_avg) {
+    if ((int)threadIdx.x >= HB) {
+      traces_axis<D, N, PDE, 0, TT, HB, HB>(P, qf, e);
+      if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, HB, HB>(P, qf, e);
+      if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, HB, HB>(P, qf, e);
+    } else {
+      euler_time_flux<D, N, PDE, HB>(P, qf, scratch);
+    }
+    __syncthreads();
+  } else if (!P.face_avg) {
     traces_axis<D, N, PDE, 0, TT, BS>(P, qf, e);
     if constexpr (D > 1) traces_axis<D, N, PDE, 1, TT, BS>(P, qf, e);
     if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
   }
-  double *us = P.ustar + e * (int64_t)(M * ND);
   if constexpr (!PDE::kElastic) {
-    if (N > 0 || P.face_avg) {
+    if (!(kHalves && !P.face_avg) && (N > 0 || P.face_avg)) {  // not yet computed by the first half
       euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
       __syncthreads();
     }
