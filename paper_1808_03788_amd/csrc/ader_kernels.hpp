@@ -1245,43 +1245,47 @@ struct Split {
   static constexpr int VPG = (M + VG - 1) / VG;
 };
 
-// Euler volume term, step 2, for axis A (one thread per line of axis A and
-// variable group):  V(v,k) += (1/h_A) sum_j Vop[k_A][j] FB[A][v](k_A = j).
-// V accumulates in place of FB[0] (the axis-0 pass reads each line before it
-// overwrites it).
-template <int D, int N, class PDE, int A, int BS>
-__device__ __forceinline__ void euler_volume_axis(PArg &P, double *FB) {
+// Euler volume term, step 2, all axes at once (the axes read and write
+// disjoint parts of FB): whole wavefronts per axis, one thread per line of
+// the axis and variable group,
+//   V_A(v,k) = (1/h_A) sum_j Vop[k_A][j] FB[A][v](k_A = j), written over FB[A].
+template <int D, int N, class PDE, int BS>
+__device__ __forceinline__ void euler_volume_axes(PArg &P, double *FB) {
   using S = Shape<D, N>;
   constexpr int n = S::n, M = PDE::M, ND = S::ND, NF = S::NF;
-  constexpr int ST = ipow(n, A);
-  using SP = Split<NF, M, BS>;
-  for (int it = threadIdx.x; it < NF * SP::VG; it += BS) {
-    const int g = it / NF, t = it - g * NF;
-    const int base = t % ST + (t / ST) * ST * n;
+  constexpr int TPA = round64(NF);  // threads per axis
+  using SP = Split<NF, M, TPA>;
+  for (int it = threadIdx.x; it < D * TPA; it += BS) {
+    const int A = __builtin_amdgcn_readfirstlane(it / TPA);  // uniform over a wavefront
+    const int r = it - A * TPA;
+    if (r < NF * SP::VG) {
+      const int g = r / NF, t = r - g * NF;
+      const int ST = A == 0 ? 1 : (A == 1 ? n : n * n);
+      const int base = t % ST + (t / ST) * ST * n;
 #pragma unroll
-    for (int vv = 0; vv < SP::VPG; vv++) {
-      const int v = g * SP::VPG + vv;
-      if (v < M) {
-        const double *src = FB + (A * M + v) * ND + base;
-        double *dst = FB + v * ND + base;
-        double f[n], acc[n];
+      for (int vv = 0; vv < SP::VPG; vv++) {
+        const int v = g * SP::VPG + vv;
+        if (v < M) {
+          double *line = FB + (A * M + v) * ND + base;
+          double f[n];
 #pragma unroll
-        for (int j = 0; j < n; j++) f[j] = src[j * ST];
+          for (int j = 0; j < n; j++) f[j] = line[j * ST];
 #pragma unroll
-        for (int k = 0; k < n; k++) acc[k] = A == 0 ? 0.0 : dst[k * ST];
+          for (int k = 0; k < n; k++) {
+            double acc = 0.0;
 #pragma unroll
-        for (int k = 0; k < n; k++)
-#pragma unroll
-          for (int j = 0; j < n; j++) acc[k] += cload(&P.sw->VA[A][k * kMaxN + j]) * f[j];
-#pragma unroll
-        for (int k = 0; k < n; k++) dst[k * ST] = acc[k];
+            for (int j = 0; j < n; j++) acc += cload(&P.sw->VA[A][k * kMaxN + j]) * f[j];
+            line[k * ST] = acc;
+          }
+        }
       }
     }
   }
 }
 
-// u* = u + dt V from the accumulated volume term V[v][k] (one thread per
-// DOF; DOF threadIdx.x + r*BS is the one whose u the thread holds in ureg[r]).
+// u* = u + dt (V_0 + ... + V_{D-1}) from the per-axis volume terms V_A[v][k]
+// at A*M*ND of V (one thread per DOF; DOF threadIdx.x + r*BS is the one
+// whose u the thread holds in ureg[r]).
 template <int D, int N, class PDE, int BS>
 __device__ __forceinline__ void ustar_update(const double *V, const double *ureg, double *us, double dt) {
   constexpr int M = PDE::M, ND = Shape<D, N>::ND;
@@ -1289,8 +1293,13 @@ __device__ __forceinline__ void ustar_update(const double *V, const double *ureg
 #pragma unroll
   for (int r = 0; r < NU; r++) {
     const int i = threadIdx.x + r * BS;
-    // dt = 0 (flagged state or t already at t_end) leaves the state untouched
-    if (i < M * ND) us[i] = dt == 0.0 ? ureg[r] : ureg[r] + dt * V[i];
+    if (i < M * ND) {
+      double vs = V[i];
+#pragma unroll
+      for (int A = 1; A < D; A++) vs += V[A * M * ND + i];
+      // dt = 0 (flagged state or t already at t_end) leaves the state untouched
+      us[i] = dt == 0.0 ? ureg[r] : ureg[r] + dt * vs;
+    }
   }
 }
 
@@ -1500,16 +1509,8 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
     if constexpr (N == 0) {
       for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
     } else {
-      euler_volume_axis<D, N, PDE, 0, BS>(P, scratch);
+      euler_volume_axes<D, N, PDE, BS>(P, scratch);
       __syncthreads();
-      if constexpr (D > 1) {
-        euler_volume_axis<D, N, PDE, 1, BS>(P, scratch);
-        __syncthreads();
-      }
-      if constexpr (D > 2) {
-        euler_volume_axis<D, N, PDE, 2, BS>(P, scratch);
-        __syncthreads();
-      }
       ustar_update<D, N, PDE, BS>(scratch, ureg, us, dt);
     }
   } else {
