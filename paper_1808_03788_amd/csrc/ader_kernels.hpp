@@ -309,9 +309,10 @@ __device__ __forceinline__ float round_bf16(float x) {
 // of the accumulator is held at (v - kAccShift) * VS.  With kHold the n x M
 // results go to held[k * M + v] (registers of the caller) instead of sacc.
 // The accumulator is stored as TA (T, or FP32 partial sums of the FP64
-// residual sweep).
+// residual sweep).  Only the output nodes KLO <= k < KHI of the line are
+// computed (the flux still at all n nodes).
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int VS, bool kAcc, int kPart = 0,
-          int kAccShift = 0, bool kHold = false, typename TA = T>
+          int kAccShift = 0, bool kHold = false, typename TA = T, int KLO = 0, int KHI = N + 1>
 __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int base, T irho, T lam, T mu,
                                          T *held = nullptr) {
   constexpr int n = N + 1, M = PDE::M;
@@ -325,7 +326,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int ba
   // the accumulated right-hand side of the earlier axes
   T acc[n][M];
 #pragma unroll
-  for (int k = 0; k < n; k++)
+  for (int k = KLO; k < KHI; k++)
 #pragma unroll
     for (int v = 0; v < M; v++)
       acc[k][v] = (kAcc && part_writes<kPart>(v)) ? (T)sacc[(v - kAccShift) * VS + base + k * ST] : T(0);
@@ -339,7 +340,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int ba
         for (int v = 0; v < M; v++) F[j][v] = round_bf16(F[j][v]);
     }
 #pragma unroll
-    for (int k = 0; k < n; k++)
+    for (int k = KLO; k < KHI; k++)
 #pragma unroll
       for (int v = 0; v < M; v++)
 #pragma unroll
@@ -351,7 +352,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int ba
 #pragma unroll
         for (int v = 0; v < M; v++) qv[j][v] = round_bf16(qv[j][v]);
 #pragma unroll
-    for (int k = 0; k < n; k++) {
+    for (int k = KLO; k < KHI; k++) {
       T gk[M], bg[M];
 #pragma unroll
       for (int v = 0; v < M; v++) {
@@ -366,7 +367,7 @@ __device__ __forceinline__ void line_rhs(PArg &P, const TQ *sq, TA *sacc, int ba
     }
   }
 #pragma unroll
-  for (int k = 0; k < n; k++)
+  for (int k = KLO; k < KHI; k++)
 #pragma unroll
     for (int v = 0; v < M; v++) {
       if constexpr (kHold)
@@ -424,10 +425,25 @@ __host__ __device__ constexpr int third_axis(int D, int N) {
 // the block takes the velocity rows of every line and the second half the
 // stress rows (whole wavefronts on each side).
 template <int D, int N, class PDE, int A, typename T, typename TQ, bool kRoundBF, int BS, bool kSplit = false,
-          bool kAcc = (A > 0), typename TA = T>
+          bool kAcc = (A > 0), typename TA = T, bool kHalfK = false>
 __device__ __forceinline__ void rhs_axis(PArg &P, const TQ *sq, TA *sacc, T irho, T lam, T mu) {
   constexpr int NS = line_slots_count<D, N>(), NST = Shape<D, N>::NST;
-  if constexpr (kSplit) {
+  if constexpr (kHalfK) {
+    // two threads per line, on two halves of whole wavefronts: the first
+    // computes the output nodes k < KH, the second the others (both
+    // evaluate the line's fluxes)
+    static_assert(!kSplit && BS >= 2 * NS, "two halves of whole wavefronts");
+    constexpr int KH = (N + 2) / 2;
+    const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
+    const int base = half < 2 ? slot_base<D, N, A>(L) : (int)kEmptySlot;
+    if (base != kEmptySlot) {
+      if (half == 0)
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc, 0, 0, false, TA, 0, KH>(P, sq, sacc, base, irho, lam, mu);
+      else
+        line_rhs<D, N, PDE, A, T, TQ, kRoundBF, NST, kAcc, 0, 0, false, TA, KH, N + 1>(P, sq, sacc, base, irho, lam,
+                                                                                       mu);
+    }
+  } else if constexpr (kSplit) {
     static_assert(BS == 2 * NS && PDE::kElastic, "two threads per line");
     const int half = threadIdx.x / NS, L = threadIdx.x - half * NS;
     const int base = slot_base<D, N, A>(L);
@@ -672,7 +688,11 @@ __device__ __forceinline__ void picard_sweep(PArg &P, const TQ *sq, TA *sacc, TO
       rhs_pair_held<D, N, PDE, T, TQ, kRoundBF, BS>(P, sq, sacc, irho, lam, mu);
     __syncthreads();
     if constexpr (D > 2) {
-      rhs_axis<D, N, PDE, third_axis(D, N), T, TQ, kRoundBF, BS, false, true, TA>(P, sq, sacc, irho, lam, mu);
+      // the third axis alone: its lines split by output nodes over the
+      // whole block (not in the 512/1024-thread blocks, whose 128
+      // registers would spill)
+      rhs_axis<D, N, PDE, third_axis(D, N), T, TQ, kRoundBF, BS, false, true, TA, (BS <= 256)>(P, sq, sacc, irho, lam,
+                                                                                              mu);
       __syncthreads();
     }
     time_phase<D, N, PDE, T, TO, BS, kPair == kPairTwo, TA>(P, sacc, qout, ureg, dt, sacc2);
