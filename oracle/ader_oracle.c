@@ -623,27 +623,30 @@ static void element_corrector(const orc_problem *p, const setup_t *s, int e, con
       for (int i = 0; i < m * nd; i++) G[i] = 0.0;
       for (int k = 0; k < nd && p->face_avg; k++) {
         if (axis_index(s, k, a) != 0) continue;
-        /* time averages of the traces, and the face values of the
-         * time-averaged nodal fluxes, on this face node */
+        /* time averages, over the time nodes, of the boundary-extrapolated
+         * states and of the flux evaluated at those states */
         double qi[MAXM], qo[MAXM], Fi[MAXM], Fo[MAXM];
         for (int v = 0; v < m; v++) qi[v] = qo[v] = Fi[v] = Fo[v] = 0.0;
-        for (int l0 = 0; l0 < n; l0++)
-          for (int j = 0; j < n; j++) {
-            const int kj = k + j * s->str[a];
-            double vin[MAXM], vout[MAXM], f1[MAXM], f2[MAXM];
-            for (int v = 0; v < m; v++) {
-              vin[v] = q[(v * n + l0) * nd + kj];
-              vout[v] = qn[(v * n + l0) * nd + kj];
+        for (int l0 = 0; l0 < n; l0++) {
+          double tin[MAXM], tout[MAXM], fin[MAXM], fout[MAXM];
+          for (int v = 0; v < m; v++) {
+            double si = 0.0, so = 0.0;
+            for (int j = 0; j < n; j++) {
+              si += phin[j] * q[(v * n + l0) * nd + k + j * s->str[a]];
+              so += phout[j] * qn[(v * n + l0) * nd + k + j * s->str[a]];
             }
-            pde_flux(p, s, vin, a, f1);
-            pde_flux(p, s, vout, a, f2);
-            for (int v = 0; v < m; v++) {
-              qi[v] += s->w[l0] * phin[j] * vin[v];
-              qo[v] += s->w[l0] * phout[j] * vout[v];
-              Fi[v] += s->w[l0] * phin[j] * f1[v];
-              Fo[v] += s->w[l0] * phout[j] * f2[v];
-            }
+            tin[v] = si;
+            tout[v] = so;
           }
+          pde_flux(p, s, tin, a, fin);
+          pde_flux(p, s, tout, a, fout);
+          for (int v = 0; v < m; v++) {
+            qi[v] += s->w[l0] * tin[v];
+            qo[v] += s->w[l0] * tout[v];
+            Fi[v] += s->w[l0] * fin[v];
+            Fo[v] += s->w[l0] * fout[v];
+          }
+        }
         double D[MAXM];
         dminus_avg(p, s, qi, qo, Fi, Fo, mat, matn, a, sgn, D);
         for (int v = 0; v < m; v++) G[v * nd + k] = D[v];

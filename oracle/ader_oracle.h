@@ -109,9 +109,9 @@ int orc_predictor_converge(const orc_problem *p, const double *u, double dt,
 /* Corrector (Sec. 2.1, eq. pde.nc.gw2): unew = u + dt*R(qhat). */
 /* With p->face_avg the face integral of every face node is taken from
  * time averages: qbar, the time average of the boundary-extrapolated state,
- * and Fbar, the boundary value of the time-averaged nodal flux
- * sum_j phi_j(side) sum_l0 w_l0 F(q(l0, node j)) (the interpolant of the
- * flux, as in the volume term, instead of the flux of the trace):
+ * and Fbar, the time average of the flux of that state,
+ * sum_l0 w_l0 F(sum_j phi_j(side) q(l0, node j)) (the flux of the trace at
+ * each time node, as in the per-time-node integral):
  *   G = 1/2 (Fbar+ + Fbar-).n + 1/2 (int_0^1 B(psi).n ds - s_max I)(qbar+ - qbar-),
  * path and s_max from the averaged states.  For elasticity (no flux; B and
  * s_max depend only on the material) this equals the per-time-node integral. */

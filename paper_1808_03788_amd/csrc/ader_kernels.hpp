@@ -1423,17 +1423,15 @@ __device__ __forceinline__ void traces_axis(PArg &P, const double *sq, int64_t e
   }
 }
 
-// Time-averaged traces of variable v at face node kf of the faces normal to
-// axis A, both sides: qbar = sum_j phi_j(side) Qbar(node j), where Qbar is
-// the time average sum_l0 w_l0 q(l0) at the volume nodes (read from qf, or
-// given as QB), and for Euler Fbar = sum_j phi_j(side) FB_A(node j), the
-// boundary value of the time-averaged nodal flux of the volume term.
-// Stored as TT in [avg_comps][NF] per element and side.
+// Time-averaged trace of variable v at face node kf of the faces normal to
+// axis A, both sides (elasticity: the jump term is linear with
+// time-independent coefficients, so qbar is all it needs): qbar =
+// sum_j phi_j(side) QB(node j), QB the time average sum_l0 w_l0 q(l0) at the
+// volume nodes.  Stored as TT in [avg_comps][NF] per element and side.
 template <int D, int N, class PDE, int A, typename TT>
-__device__ __forceinline__ void trace_avg_value(PArg &P, const double *qf, const double *QB, const double *FB,
-                                                int64_t e, int v, int kf) {
+__device__ __forceinline__ void trace_avg_value(PArg &P, const double *QB, int64_t e, int v, int kf) {
   using S = Shape<D, N>;
-  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int n = S::n, ND = S::ND, NF = S::NF;
   constexpr int ST = ipow(n, A), NC = avg_comps<PDE>();
   const int base = kf % ST + (kf / ST) * ST * n;
   TT *t0 = (TT *)P.trace[A][0] + e * (int64_t)(NC * NF) + kf;
@@ -1441,46 +1439,90 @@ __device__ __forceinline__ void trace_avg_value(PArg &P, const double *qf, const
   double a0 = 0.0, a1 = 0.0;
 #pragma unroll
   for (int j = 0; j < n; j++) {
-    double qb;
-    if (QB) {
-      qb = QB[v * ND + base + j * ST];
-    } else {
-      qb = 0.0;
-#pragma unroll
-      for (int l0 = 0; l0 < n; l0++) qb += cload(&P.ops->w[l0]) * qf[v * NST + l0 * ND + base + j * ST];
-    }
+    const double qb = QB[v * ND + base + j * ST];
     a0 += cload(&P.ops->F0[j]) * qb;
     a1 += cload(&P.ops->F1[j]) * qb;
   }
   t0[v * NF] = (TT)a0;
   t1[v * NF] = (TT)a1;
-  if constexpr (!PDE::kElastic) {
-    double f0 = 0.0, f1 = 0.0;
-#pragma unroll
-    for (int j = 0; j < n; j++) {
-      const double fb = FB[(A * M + v) * ND + base + j * ST];
-      f0 += cload(&P.ops->F0[j]) * fb;
-      f1 += cload(&P.ops->F1[j]) * fb;
-    }
-    t0[(M + v) * NF] = (TT)f0;
-    t1[(M + v) * NF] = (TT)f1;
-  }
 }
 
-// Averaged traces of all 2D faces: one thread per (axis, variable, face
-// node), both sides.
+// Averaged traces of all 2D faces for elasticity: one thread per (axis,
+// variable, face node), both sides.
 template <int D, int N, class PDE, typename TT, int BS>
-__device__ __forceinline__ void traces_avg(PArg &P, const double *qf, const double *QB, const double *FB,
-                                           int64_t e) {
+__device__ __forceinline__ void traces_avg(PArg &P, const double *QB, int64_t e) {
   constexpr int M = PDE::M, NF = Shape<D, N>::NF;
   for (int it = threadIdx.x; it < D * M * NF; it += BS) {
     const int A = it / (M * NF), r = it - A * (M * NF);
     const int v = r / NF, kf = r - v * NF;
-    if (A == 0) trace_avg_value<D, N, PDE, 0, TT>(P, qf, QB, FB, e, v, kf);
+    if (A == 0) trace_avg_value<D, N, PDE, 0, TT>(P, QB, e, v, kf);
     else if (A == 1) {
-      if constexpr (D > 1) trace_avg_value<D, N, PDE, 1, TT>(P, qf, QB, FB, e, v, kf);
+      if constexpr (D > 1) trace_avg_value<D, N, PDE, 1, TT>(P, QB, e, v, kf);
     } else {
-      if constexpr (D > 2) trace_avg_value<D, N, PDE, 2, TT>(P, qf, QB, FB, e, v, kf);
+      if constexpr (D > 2) trace_avg_value<D, N, PDE, 2, TT>(P, QB, e, v, kf);
+    }
+  }
+}
+
+// Time-averaged Euler trace at face node kf of the faces normal to axis A
+// on one side (0: the face at xi = 0): at each time node l0 the trace
+// t(l0) = sum_j phi_j(side) q(l0, node j) of every variable and its flux
+// F_A(t(l0)); stored are qbar = sum_l0 w_l0 t(l0) and Fbar = sum_l0 w_l0
+// F_A(t(l0)), so that the averaged central flux equals the time integral of
+// the per-time-node one.  Layout as trace_avg_value.
+template <int D, int N, class PDE, int A, typename TT>
+__device__ __forceinline__ void trace_avg_euler(PArg &P, const double *qf, int64_t e, int side, int kf) {
+  using S = Shape<D, N>;
+  constexpr int n = S::n, M = PDE::M, ND = S::ND, NST = S::NST, NF = S::NF;
+  constexpr int ST = ipow(n, A), NC = avg_comps<PDE>();
+  const int base = kf % ST + (kf / ST) * ST * n;
+  const double *phi = side ? P.ops->F1 : P.ops->F0;
+  const double gm1 = P.g.gamma - 1.0;
+  double qb[M], fb[M];
+#pragma unroll
+  for (int v = 0; v < M; v++) qb[v] = fb[v] = 0.0;
+  // loops kept rolled: this phase must not raise the kernel's register count
+#pragma unroll 1
+  for (int l0 = 0; l0 < n; l0++) {
+    double t[M], F[M];
+#pragma unroll
+    for (int v = 0; v < M; v++) t[v] = 0.0;
+#pragma unroll 1
+    for (int j = 0; j < n; j++) {
+      const double pj = cload(&phi[j]);
+      const double *qj = qf + l0 * ND + base + j * ST;
+#pragma unroll
+      for (int v = 0; v < M; v++) t[v] += pj * qj[v * NST];
+    }
+    euler_flux<D, A, double>(t, gm1, F);
+    const double wl = cload(&P.ops->w[l0]);
+#pragma unroll
+    for (int v = 0; v < M; v++) {
+      qb[v] += wl * t[v];
+      fb[v] += wl * F[v];
+    }
+  }
+  TT *o = (TT *)P.trace[A][side] + e * (int64_t)(NC * NF) + kf;
+#pragma unroll
+  for (int v = 0; v < M; v++) {
+    o[v * NF] = (TT)qb[v];
+    o[(M + v) * NF] = (TT)fb[v];
+  }
+}
+
+// Averaged Euler traces of all 2D faces: one thread per (axis, side, face
+// node).
+template <int D, int N, class PDE, typename TT, int BS>
+__device__ __forceinline__ void traces_avg_euler(PArg &P, const double *qf, int64_t e) {
+  constexpr int NF = Shape<D, N>::NF;
+  for (int it = threadIdx.x; it < D * 2 * NF; it += BS) {
+    const int A = it / (2 * NF), r = it - A * (2 * NF);
+    const int side = r / NF, kf = r - side * NF;
+    if (A == 0) trace_avg_euler<D, N, PDE, 0, TT>(P, qf, e, side, kf);
+    else if (A == 1) {
+      if constexpr (D > 1) trace_avg_euler<D, N, PDE, 1, TT>(P, qf, e, side, kf);
+    } else {
+      if constexpr (D > 2) trace_avg_euler<D, N, PDE, 2, TT>(P, qf, e, side, kf);
     }
   }
 }
@@ -1518,12 +1560,9 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
     if constexpr (D > 2) traces_axis<D, N, PDE, 2, TT, BS>(P, qf, e);
   }
   if constexpr (!PDE::kElastic) {
-    if (!(kHalves && !P.face_avg) && (N > 0 || P.face_avg)) {  // not yet computed by the first half
+    if (P.face_avg) traces_avg_euler<D, N, PDE, TT, BS>(P, qf, e);  // reads qf only
+    if (!(kHalves && !P.face_avg) && N > 0) {  // not yet computed by the first half
       euler_time_flux<D, N, PDE, BS>(P, qf, scratch);
-      __syncthreads();
-    }
-    if (P.face_avg) {  // before the volume passes overwrite FB[0]
-      traces_avg<D, N, PDE, TT, BS>(P, qf, nullptr, scratch, e);
       __syncthreads();
     }
     if constexpr (N == 0) {
@@ -1542,7 +1581,7 @@ __device__ __forceinline__ void predictor_outputs(PArg &P, const double *qf, dou
       scratch[i] = a;
     }
     __syncthreads();
-    if (P.face_avg) traces_avg<D, N, PDE, TT, BS>(P, qf, scratch, nullptr, e);
+    if (P.face_avg) traces_avg<D, N, PDE, TT, BS>(P, scratch, e);
     if constexpr (N == 0) {
       for (int i = threadIdx.x; i < M * ND; i += BS) us[i] = ue[i];  // no volume term at N = 0
     } else {
