@@ -1481,13 +1481,14 @@ __device__ __forceinline__ void trace_avg_euler(PArg &P, const double *qf, int64
   double qb[M], fb[M];
 #pragma unroll
   for (int v = 0; v < M; v++) qb[v] = fb[v] = 0.0;
-  // loops kept rolled: this phase must not raise the kernel's register count
+  // the time loop kept rolled (one time node's loads in flight at once, but
+  // no more: this phase must not raise the kernel's register count)
 #pragma unroll 1
   for (int l0 = 0; l0 < n; l0++) {
     double t[M], F[M];
 #pragma unroll
     for (int v = 0; v < M; v++) t[v] = 0.0;
-#pragma unroll 1
+#pragma unroll
     for (int j = 0; j < n; j++) {
       const double pj = cload(&phi[j]);
       const double *qj = qf + l0 * ND + base + j * ST;
