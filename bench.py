@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "DOF-updates/sec/GPU for ADER-DG step, FP32-MFMA vs FP64, at stated L2 error"
 # MI355X peaks (TFLOP/s, GB/s), AMD's published dense figures: FP64 (vector =
 # matrix) 78.6, FP32 157.3 (matrix; the vector rate needs packed FP32
-# instructions, which this build does not use: 78.6 without them), BF16
+# instructions, which the library is compiled without: 78.6 without them), BF16
 # matrix 2500, HBM3E 8000 GB/s.
 PEAK = {"fp64": 78.6, "fp32": 157.3, "bf16": 2500.0, "fp32_valu_unpacked": 78.6, "hbm": 8000.0}
 # Flop conventions of the algorithmic work model: c_F flops per Euler flux

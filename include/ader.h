@@ -108,7 +108,8 @@ typedef struct {
                            Guesses 1 to 3 are computed in the sweeps' precision. */
   int32_t face_avg;     /* 0: the jump term at every face node and time node, integrated in
                            time (eqs. pc.scheme, rusanov); 1: from time-averaged traces,
-                           qbar = sum w_l q(l) and (Euler) Fbar = sum w_l F(q(l)):
+                           qbar = sum w_l q(l) and (Euler) Fbar = sum w_l F(q(l)), q(l) the
+                           face trace at time node l:
                            G = 1/2 (Fbar+ + Fbar-).n + 1/2 (path - s_max)(qbar+ - qbar-),
                            s_max from the averaged states.  Exact for elasticity (linear,
                            time-independent coefficients); for Euler only the Rusanov speed
