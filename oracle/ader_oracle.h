@@ -21,9 +21,12 @@
  *   qhat[e][v][l0][k]   space-time predictor DOFs, l0 = time node
  *
  * Parity status: every function below is pinned by a CPU test (see the
- * oracle tests) except the absolute error values of the isentropic vortex,
- * which the paper quotes from another work without its parameters
- * (parity unpinned for those absolute values; only the orders are pinned).
+ * oracle tests).  The absolute error values of the isentropic vortex, which
+ * the paper quotes from another work without the vortex parameters, final
+ * time or error variable, are compared only loosely (density L2 error within
+ * a factor of 3 of the printed values at the two coarsest meshes of
+ * N = 3, 4, 5, with the parameters the tests assume); their orders are
+ * pinned.
  */
 #ifndef ADER_ORACLE_H
 #define ADER_ORACLE_H
